@@ -1,0 +1,630 @@
+/*
+ * oracle.c -- plain, slow FP64 CPU reference for one time step of the
+ * dimensionally split high-resolution finite-volume method for the
+ * nonlinear thermoviscous acoustic balance laws of Velasco-Segura & Rendon,
+ * "A Finite Volume Approach for the Simulation of Nonlinear Dissipative
+ * Acoustic Wave Propagation" (arXiv:1311.3004).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the parity oracle: it is called by
+ * the test-suite, by the smoke check and by the CPU-baseline leg of the
+ * benchmark, never by the product library.  It shares no code, header, table
+ * or helper with the HIP path.  Compile with -ffp-contract=off (no FMA
+ * contraction) so that every operation below rounds exactly as written.
+ *
+ * Units.  Lengths are measured in cells (the reference length L of the
+ * paper's renormalisation, Sec. 3 eq. renorm, is taken as the mesh spacing,
+ * so Delta x = 1) and time in units of Delta x / c0.  The state is stored in
+ * perturbation form: R = q^1 - 1 = rho'/rho0, M = q^2, N = q^3 (eq. adim:q).
+ * Carrying R instead of q^1 is an exact change of variable that keeps the
+ * relative precision of small perturbations; every formula of the paper that
+ * uses q^1 is written with q^1 = 1 + R.
+ *
+ * Step (Sec. 3, eqs. fs:cl1, fs:cl2, fs:source, applied one after another):
+ *   ghosts(x) of Q^n -> x1 sweep -> ghosts(y) of Q* -> x2 sweep (components
+ *   2 and 3 swapped) -> one ghost layer of Q** -> source -> Q^{n+1};
+ *   then the CFL number of the step decides acceptance (Sec. 4 opening).
+ *
+ * Readings of points the paper leaves open are stated where they are used.
+ * Parity status of each function is stated in its comment; the pins that fix
+ * each one live in the test-suite.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+enum { ORC_OK = 0, ORC_E_INVALID = 1, ORC_E_NOMEM = 2, ORC_E_NONHYPERBOLIC = 4,
+       ORC_E_NONFINITE = 5, ORC_E_RETRIES = 6 };
+enum { BC_PERIODIC = 0, BC_EXTRAP0 = 1, BC_REFLECT = 2, BC_TAYLOR = 3, BC_SOURCE = 4 };
+enum { GEOM_PLANAR = 0, GEOM_AXISYM = 1 };
+
+/* All quantities dimensionless (cells, Delta x / c0). */
+typedef struct {
+    int nx, ny;
+    double beta;            /* coefficient of nonlinearity, beta = 1 + B/2A          */
+    double delta;           /* delta~ = delta / (c0 Delta x)   (eq. phi-tdelta)       */
+    int geometry;           /* GEOM_PLANAR or GEOM_AXISYM (x1 = z, x2 = r)            */
+    int bc[4];              /* sides x-, x+, y-, y+                                   */
+    double cfl_target;      /* nu_W                                                   */
+    double cfl_max;         /* a step with nu > cfl_max is rejected and redone        */
+    int max_retries;
+    int fixed_dt;           /* 1: never change dt (parity runs); nu still recorded    */
+    /* analytic Taylor shock-like profile used by BC_TAYLOR (eq. OurTaylorS) */
+    double taylor_amp, taylor_width, taylor_x0, taylor_y0, taylor_angle;
+    /* focused boundary source used by BC_SOURCE on side x- (eq. hifuBC)      */
+    double src_amp, src_freq, src_focal, src_aperture, src_ramp_cycles;
+} orc_params;
+
+typedef struct {
+    double t, dt_next, nu_last, nu_mean, nu_std;
+    long steps, rejected;
+    int status;
+    long status_step;
+} orc_stats;
+
+/* ------------------------------------------------------------------------- */
+/* Flux and pressure-like function (eq. adim:q).  Exported for the pins.     */
+/* ------------------------------------------------------------------------- */
+
+/* phi(q^1) = q^1 + (beta-1)(q^1-1)^2, returned minus its ambient value 1 so
+ * that flux differences keep the precision of the perturbations. */
+static double phi_excess(double beta, double R) { return R + (beta - 1.0) * R * R; }
+
+/* x1-flux f_1(q) = (q^2, (q^2)^2/(q^1)^2 + phi, q^2 q^3/(q^1)^2), with the
+ * constant ambient part of phi removed (it cancels in every difference). */
+void orc_flux(double beta, const double q[3], double f[3])
+{
+    double q1 = 1.0 + q[0];
+    f[0] = q[1];
+    f[1] = q[1] * q[1] / (q1 * q1) + phi_excess(beta, q[0]);
+    f[2] = q[1] * q[2] / (q1 * q1);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Roe linearisation (Sec. 3.2).                                             */
+/* ------------------------------------------------------------------------- */
+
+/* Solve the 3x3 system A x = b by Gaussian elimination with partial pivoting.
+ * Returns 0 if the matrix is singular. */
+static int solve3(double A[3][3], double b[3], double x[3])
+{
+    double a[3][4];
+    for (int i = 0; i < 3; i++) {
+        for (int j = 0; j < 3; j++) a[i][j] = A[i][j];
+        a[i][3] = b[i];
+    }
+    for (int c = 0; c < 3; c++) {
+        int piv = c;
+        for (int r = c + 1; r < 3; r++)
+            if (fabs(a[r][c]) > fabs(a[piv][c])) piv = r;
+        if (a[piv][c] == 0.0) return 0;
+        if (piv != c)
+            for (int j = 0; j < 4; j++) { double t = a[c][j]; a[c][j] = a[piv][j]; a[piv][j] = t; }
+        for (int r = c + 1; r < 3; r++) {
+            double f = a[r][c] / a[c][c];
+            for (int j = c; j < 4; j++) a[r][j] = a[r][j] - f * a[c][j];
+        }
+    }
+    for (int r = 2; r >= 0; r--) {
+        double s = a[r][3];
+        for (int j = r + 1; j < 3; j++) s = s - a[r][j] * x[j];
+        x[r] = s / a[r][r];
+    }
+    return 1;
+}
+
+/* Roe decomposition at one interface, for the x1 direction.
+ * qL, qR: (R, M_normal, M_tangential) of the left and right cells.
+ * Outputs: speeds s[p], eigenvectors r[p][c], strengths alpha[p], waves
+ * W[p][c] = alpha[p] r[p][c], fluctuations amdq = sum_p min(s,0) W, apdq =
+ * sum_p max(s,0) W (eqs. fluc:m, fluc:p).  Returns 1 if the eigenvalues are
+ * real and distinct (discriminant > 0), 0 otherwise (outputs then undefined).
+ *
+ * Z-bar is the arithmetic mean of z = (q^1, q^2/q^1, q^3/q^1) of the two
+ * cells; Phi = 1 + 2(beta-1)(Zbar^1 - 1); eigenvalues per eqs. lambda1-3.
+ * Eigenvectors: the paper only says they follow directly; the form used here
+ * is the kernel of (A-hat - s I): r = (1, s, Zbar^3 (s - 2 Zbar^2)/(Zbar^1 (s - Zbar^2/Zbar^1)))
+ * for the two acoustic speeds, and (0, 0, 1) for s^3.  The strengths alpha
+ * come from solving sum_p alpha^p r^p = Q_R - Q_L as a linear system. */
+int orc_roe(double beta, const double qL[3], const double qR[3],
+            double s[3], double r[3][3], double alpha[3], double W[3][3],
+            double amdq[3], double apdq[3])
+{
+    double q1L = 1.0 + qL[0], q1R = 1.0 + qR[0];
+    double z2L = qL[1] / q1L, z3L = qL[2] / q1L;
+    double z2R = qR[1] / q1R, z3R = qR[2] / q1R;
+    double Zb1m1 = 0.5 * (qL[0] + qR[0]);          /* Zbar^1 - 1 */
+    double Zb1 = 1.0 + Zb1m1;
+    double Zb2 = 0.5 * (z2L + z2R);
+    double Zb3 = 0.5 * (z3L + z3R);
+    double Phi = 1.0 + 2.0 * (beta - 1.0) * Zb1m1;
+    double w = Zb2 / Zb1;
+    double disc = (Zb2 * Zb2) / (Zb1 * Zb1) - 2.0 * (Zb2 * Zb2) / Zb1 + Phi;
+    if (!(disc > 0.0)) return 0;
+    double root = sqrt(disc);
+    s[0] = w + root;
+    s[1] = w - root;
+    s[2] = w;
+    for (int p = 0; p < 2; p++) {
+        r[p][0] = 1.0;
+        r[p][1] = s[p];
+        r[p][2] = Zb3 * (s[p] - 2.0 * Zb2) / (Zb1 * (s[p] - w));
+    }
+    r[2][0] = 0.0; r[2][1] = 0.0; r[2][2] = 1.0;
+    double Rm[3][3], dq[3];
+    for (int c = 0; c < 3; c++) {
+        for (int p = 0; p < 3; p++) Rm[c][p] = r[p][c];
+        dq[c] = qR[c] - qL[c];
+    }
+    if (!solve3(Rm, dq, alpha)) return 0;
+    for (int c = 0; c < 3; c++) { amdq[c] = 0.0; apdq[c] = 0.0; }
+    for (int p = 0; p < 3; p++) {
+        double sm = s[p] < 0.0 ? s[p] : 0.0;
+        double sp = s[p] > 0.0 ? s[p] : 0.0;
+        for (int c = 0; c < 3; c++) {
+            W[p][c] = alpha[p] * r[p][c];
+            amdq[c] = amdq[c] + sm * W[p][c];
+            apdq[c] = apdq[c] + sp * W[p][c];
+        }
+    }
+    return 1;
+}
+
+/* Monotonized central-difference limiter (Sec. 3.1, below eq. limiter). */
+double orc_mc(double theta)
+{
+    double a = (1.0 + theta) / 2.0;
+    double b = 2.0;
+    double c = 2.0 * theta;
+    double m = a < b ? a : b;
+    m = m < c ? m : c;
+    return m > 0.0 ? m : 0.0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* One-dimensional high-resolution sweep (Sec. 3.1, eq. fv-hr).              */
+/* ------------------------------------------------------------------------- */
+
+/* Per-interface data of one line. */
+typedef struct { double s[3], W[3][3], amdq[3], apdq[3]; int ok; } iface_t;
+
+/* Update n interior cells of one line.  Input arrays hold n + 4 values: two
+ * ghost cells, the n interior cells, two ghost cells (index k = i + 2 for
+ * cell i).  qn is the normal momentum, qt the tangential one.  Writes the
+ * n updated interior values to the out arrays.  *smax is raised to the
+ * largest |s^p| over the interfaces i - 1/2, i = 0..n (those adjacent to an
+ * interior cell); *bad is set if one of them has non-real speeds. */
+static int sweep_line(double beta, double dtdx, int n,
+                      const double *qr, const double *qn, const double *qt,
+                      double *outr, double *outn, double *outt,
+                      iface_t *f, double *smax, int *bad)
+{
+    /* interface i - 1/2 for i = -1..n+1 stored at f[i + 1] */
+    for (int i = -1; i <= n + 1; i++) {
+        int kl = i + 1, kr = i + 2;     /* cells i-1 and i */
+        double qL[3] = { qr[kl], qn[kl], qt[kl] };
+        double qR[3] = { qr[kr], qn[kr], qt[kr] };
+        double r[3][3], alpha[3];
+        iface_t *F = &f[i + 1];
+        F->ok = orc_roe(beta, qL, qR, F->s, r, alpha, F->W, F->amdq, F->apdq);
+        if (!F->ok) {
+            for (int p = 0; p < 3; p++) {
+                F->s[p] = NAN;
+                for (int c = 0; c < 3; c++) F->W[p][c] = NAN;
+            }
+            for (int c = 0; c < 3; c++) { F->amdq[c] = NAN; F->apdq[c] = NAN; }
+        }
+        if (i >= 0 && i <= n) {
+            if (!F->ok) *bad = 1;
+            for (int p = 0; p < 3; p++) {
+                double a = fabs(F->s[p]);
+                if (isnan(a) || a > *smax) *smax = a;
+            }
+        }
+    }
+    /* high-resolution correction F~_{i-1/2} for i = 0..n (eq. limiter) */
+    double (*Ft)[3] = malloc(sizeof(double[3]) * (size_t)(n + 1));
+    if (!Ft) return ORC_E_NOMEM;
+    for (int i = 0; i <= n; i++) {
+        const iface_t *F = &f[i + 1];
+        for (int c = 0; c < 3; c++) Ft[i][c] = 0.0;
+        for (int p = 0; p < 3; p++) {
+            /* upwind interface I - 1/2: I = i - 1 if s > 0, i + 1 if s < 0.
+             * When s = 0 the term is multiplied by |s| = 0; i - 1 is used. */
+            const iface_t *U = (F->s[p] < 0.0) ? &f[i + 2] : &f[i];
+            double num = 0.0, den = 0.0;
+            for (int c = 0; c < 3; c++) {
+                num = num + U->W[p][c] * F->W[p][c];
+                den = den + F->W[p][c] * F->W[p][c];
+            }
+            double theta = (den == 0.0) ? 0.0 : num / den;
+            double phi = orc_mc(theta);
+            double as = fabs(F->s[p]);
+            double coef = 0.5 * as * (1.0 - dtdx * as);
+            for (int c = 0; c < 3; c++)
+                Ft[i][c] = Ft[i][c] + coef * (phi * F->W[p][c]);
+        }
+    }
+    /* cell update (eq. fv-hr), interface i-1/2 -> Ft[i], f[i+1] */
+    for (int i = 0; i < n; i++) {
+        const iface_t *Fl = &f[i + 1], *Fr = &f[i + 2];
+        double q[3] = { qr[i + 2], qn[i + 2], qt[i + 2] };
+        double o[3];
+        for (int c = 0; c < 3; c++)
+            o[c] = q[c] - dtdx * (Fr->amdq[c] + Fl->apdq[c]) - dtdx * (Ft[i + 1][c] - Ft[i][c]);
+        outr[i] = o[0]; outn[i] = o[1]; outt[i] = o[2];
+    }
+    free(Ft);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Grid with ghost frame and boundary conditions.                            */
+/* ------------------------------------------------------------------------- */
+
+#define GH 2
+typedef struct { int nx, ny, pitch; double *R, *M, *N; } field_t;
+
+static size_t idx(const field_t *g, int i, int j) { return (size_t)(j + GH) * (size_t)g->pitch + (size_t)(i + GH); }
+
+static int field_alloc(field_t *g, int nx, int ny)
+{
+    g->nx = nx; g->ny = ny; g->pitch = nx + 2 * GH;
+    size_t n = (size_t)g->pitch * (size_t)(ny + 2 * GH);
+    g->R = calloc(n, sizeof(double));
+    g->M = calloc(n, sizeof(double));
+    g->N = calloc(n, sizeof(double));
+    return (g->R && g->M && g->N) ? ORC_OK : ORC_E_NOMEM;
+}
+
+static void field_free(field_t *g) { free(g->R); free(g->M); free(g->N); }
+
+/* Taylor shock-like profile (eq. OurTaylorS, rotated by the angle theta_T as
+ * described in Sec. 4.1): R = -A tanh((xi - t)/w), momentum = R (cos, sin),
+ * with xi the distance along the propagation direction. */
+static void taylor_value(const orc_params *p, double x, double y, double t, double q[3])
+{
+    double ca = cos(p->taylor_angle), sa = sin(p->taylor_angle);
+    double xi = (x - p->taylor_x0) * ca + (y - p->taylor_y0) * sa;
+    double R = -p->taylor_amp * tanh((xi - t) / p->taylor_width);
+    q[0] = R; q[1] = R * ca; q[2] = R * sa;
+}
+
+/* Focused boundary source (eq. hifuBC) at distance r from the symmetry line,
+ * with the envelope replaced by a sin^2 ramp over src_ramp_cycles periods. */
+static double source_g(const orc_params *p, double r, double t)
+{
+    double f = p->src_freq;
+    double tau = t + r * r / (2.0 * p->src_focal);
+    double env;
+    double tr = p->src_ramp_cycles / f;
+    if (t <= 0.0) env = 0.0;
+    else if (t < tr) { double s = sin(M_PI * f * t / (2.0 * p->src_ramp_cycles)); env = s * s; }
+    else env = 1.0;
+    return p->src_amp * env * sin(2.0 * M_PI * f * tau);
+}
+
+/* Ghost cell (gi, gj) on the given side, layer g (1 = adjacent), at time t.
+ * side 0: x-, 1: x+, 2: y-, 3: y+.  Source cell rules (Sec. 4.2 and the
+ * periodic extension): periodic wrap; zero-order extrapolation copies the
+ * nearest interior cell; reflection mirrors the interior and negates the
+ * momentum normal to the side; Taylor and source are analytic. */
+static void set_ghost(const orc_params *p, double t, field_t *g, int side, int gi, int gj, int layer)
+{
+    int nx = g->nx, ny = g->ny;
+    int bc = p->bc[side];
+    size_t d = idx(g, gi, gj);
+    double x = gi + 0.5, y = gj + 0.5;
+    if (bc == BC_TAYLOR) {
+        double q[3];
+        taylor_value(p, x, y, t, q);
+        g->R[d] = q[0]; g->M[d] = q[1]; g->N[d] = q[2];
+        return;
+    }
+    if (bc == BC_SOURCE) {   /* valid on side x- only (checked at entry) */
+        double r = y;
+        if (r <= p->src_aperture) {
+            double gg = source_g(p, r, t);
+            double h = sqrt(r * r + p->src_focal * p->src_focal);
+            g->R[d] = gg;
+            g->M[d] = p->src_focal * gg / h;
+            g->N[d] = -r * gg / h;
+            return;
+        }
+        bc = BC_EXTRAP0;
+    }
+    int si = gi, sj = gj;
+    int xside = side < 2;
+    if (bc == BC_PERIODIC) {
+        if (side == 0) si = nx - layer;
+        if (side == 1) si = layer - 1;
+        if (side == 2) sj = ny - layer;
+        if (side == 3) sj = layer - 1;
+    } else if (bc == BC_EXTRAP0) {
+        if (side == 0) si = 0;
+        if (side == 1) si = nx - 1;
+        if (side == 2) sj = 0;
+        if (side == 3) sj = ny - 1;
+    } else { /* BC_REFLECT */
+        if (side == 0) si = layer - 1;
+        if (side == 1) si = nx - layer;
+        if (side == 2) sj = layer - 1;
+        if (side == 3) sj = ny - layer;
+    }
+    size_t s = idx(g, si, sj);
+    g->R[d] = g->R[s];
+    g->M[d] = g->M[s];
+    g->N[d] = g->N[s];
+    if (bc == BC_REFLECT) {
+        if (xside) g->M[d] = -g->M[d];
+        else g->N[d] = -g->N[d];
+    }
+}
+
+static void fill_ghosts_x(const orc_params *p, double t, field_t *g, int layers)
+{
+    for (int j = 0; j < g->ny; j++)
+        for (int l = 1; l <= layers; l++) {
+            set_ghost(p, t, g, 0, -l, j, l);
+            set_ghost(p, t, g, 1, g->nx - 1 + l, j, l);
+        }
+}
+
+static void fill_ghosts_y(const orc_params *p, double t, field_t *g, int layers)
+{
+    for (int i = 0; i < g->nx; i++)
+        for (int l = 1; l <= layers; l++) {
+            set_ghost(p, t, g, 2, i, -l, l);
+            set_ghost(p, t, g, 3, i, g->ny - 1 + l, l);
+        }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Source step (eq. fs:source): forward Euler in time, second-order central  */
+/* differences in space.                                                     */
+/* ------------------------------------------------------------------------- */
+
+/* Planar: psi = delta~ (0, lap(q^2/q^1), lap(q^3/q^1)) (eq. adim:q), read as
+ * the Laplacian of the velocity u = q^2/q^1, as the physical right-hand side
+ * rho0 delta lap(u) of eq. OurSystem requires.
+ * Axisymmetric (x1 = z, x2 = r, r_j = j + 1/2; not in the paper, derived from
+ * eq. OurSystem in cylindrical coordinates without swirl): the divergence of
+ * rho0 u(x)u + pI adds -N/r to the mass equation and -u v/r, -v^2/r to the
+ * momenta; the vector Laplacian adds (1/r) d/dr of each velocity component
+ * and -v/r^2 to the radial one.  Parity of this branch rests on the
+ * spherical-wave pin, not on the paper. */
+static void source_step(const orc_params *p, double dt, field_t *in, field_t *out)
+{
+    int nx = in->nx, ny = in->ny;
+    size_t n = (size_t)in->pitch * (size_t)(ny + 2 * GH);
+    double *u = malloc(n * sizeof(double));
+    double *v = malloc(n * sizeof(double));
+    for (size_t k = 0; k < n; k++) {
+        double q1 = 1.0 + in->R[k];
+        u[k] = in->M[k] / q1;
+        v[k] = in->N[k] / q1;
+    }
+    for (int j = 0; j < ny; j++)
+        for (int i = 0; i < nx; i++) {
+            size_t c = idx(in, i, j);
+            size_t xm = idx(in, i - 1, j), xp = idx(in, i + 1, j);
+            size_t ym = idx(in, i, j - 1), yp = idx(in, i, j + 1);
+            double lapu = u[xp] + u[xm] + u[yp] + u[ym] - 4.0 * u[c];
+            double lapv = v[xp] + v[xm] + v[yp] + v[ym] - 4.0 * v[c];
+            double sR = 0.0, sM, sN;
+            if (p->geometry == GEOM_AXISYM) {
+                double r = j + 0.5;
+                double dur = (u[yp] - u[ym]) / 2.0;
+                double dvr = (v[yp] - v[ym]) / 2.0;
+                sR = -in->N[c] / r;
+                sM = -u[c] * v[c] / r + p->delta * (lapu + dur / r);
+                sN = -v[c] * v[c] / r + p->delta * (lapv + dvr / r - v[c] / (r * r));
+            } else {
+                sM = p->delta * lapu;
+                sN = p->delta * lapv;
+            }
+            out->R[c] = in->R[c] + dt * sR;
+            out->M[c] = in->M[c] + dt * sM;
+            out->N[c] = in->N[c] + dt * sN;
+        }
+    free(u);
+    free(v);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Full step and driver.                                                     */
+/* ------------------------------------------------------------------------- */
+
+typedef struct { field_t a, b, c, d; double *lr, *ln, *lt, *or_, *on, *ot; iface_t *f; } work_t;
+
+static int work_alloc(work_t *w, int nx, int ny)
+{
+    memset(w, 0, sizeof(*w));
+    int e = field_alloc(&w->a, nx, ny) | field_alloc(&w->b, nx, ny) |
+            field_alloc(&w->c, nx, ny) | field_alloc(&w->d, nx, ny);
+    int m = (nx > ny ? nx : ny) + 2 * GH;
+    w->lr = malloc(sizeof(double) * m); w->ln = malloc(sizeof(double) * m); w->lt = malloc(sizeof(double) * m);
+    w->or_ = malloc(sizeof(double) * m); w->on = malloc(sizeof(double) * m); w->ot = malloc(sizeof(double) * m);
+    w->f = malloc(sizeof(iface_t) * (size_t)(m + 1));
+    if (e || !w->lr || !w->ln || !w->lt || !w->or_ || !w->on || !w->ot || !w->f) return ORC_E_NOMEM;
+    return ORC_OK;
+}
+
+static void work_free(work_t *w)
+{
+    field_free(&w->a); field_free(&w->b); field_free(&w->c); field_free(&w->d);
+    free(w->lr); free(w->ln); free(w->lt); free(w->or_); free(w->on); free(w->ot); free(w->f);
+}
+
+/* One attempted step from w->a (interior holds Q^n) to w->d (Q^{n+1}) with
+ * time step dt at time t.  Returns the largest |s^p| over both sweeps in
+ * *smax and 1 in *bad if any counted interface had non-real speeds. */
+static int attempt(const orc_params *p, work_t *w, double t, double dt, double *smax, int *bad)
+{
+    int nx = p->nx, ny = p->ny, e;
+    *smax = 0.0; *bad = 0;
+    /* x1 sweep on Q^n */
+    fill_ghosts_x(p, t, &w->a, 2);
+    for (int j = 0; j < ny; j++) {
+        for (int k = 0; k < nx + 2 * GH; k++) {
+            size_t s = idx(&w->a, k - GH, j);
+            w->lr[k] = w->a.R[s]; w->ln[k] = w->a.M[s]; w->lt[k] = w->a.N[s];
+        }
+        e = sweep_line(p->beta, dt, nx, w->lr, w->ln, w->lt, w->or_, w->on, w->ot, w->f, smax, bad);
+        if (e) return e;
+        for (int i = 0; i < nx; i++) {
+            size_t d = idx(&w->b, i, j);
+            w->b.R[d] = w->or_[i]; w->b.M[d] = w->on[i]; w->b.N[d] = w->ot[i];
+        }
+    }
+    /* x2 sweep on Q*: same scheme with components 2 and 3 swapped */
+    fill_ghosts_y(p, t, &w->b, 2);
+    for (int i = 0; i < nx; i++) {
+        for (int k = 0; k < ny + 2 * GH; k++) {
+            size_t s = idx(&w->b, i, k - GH);
+            w->lr[k] = w->b.R[s]; w->ln[k] = w->b.N[s]; w->lt[k] = w->b.M[s];
+        }
+        e = sweep_line(p->beta, dt, ny, w->lr, w->ln, w->lt, w->or_, w->on, w->ot, w->f, smax, bad);
+        if (e) return e;
+        for (int j = 0; j < ny; j++) {
+            size_t d = idx(&w->c, i, j);
+            w->c.R[d] = w->or_[j]; w->c.N[d] = w->on[j]; w->c.M[d] = w->ot[j];
+        }
+    }
+    /* source on Q** with one ghost layer */
+    fill_ghosts_x(p, t, &w->c, 1);
+    fill_ghosts_y(p, t, &w->c, 1);
+    source_step(p, dt, &w->c, &w->d);
+    return ORC_OK;
+}
+
+static int check_params(const orc_params *p)
+{
+    if (p->nx < 4 || p->ny < 4) return ORC_E_INVALID;
+    if (p->bc[1] == BC_SOURCE || p->bc[2] == BC_SOURCE || p->bc[3] == BC_SOURCE) return ORC_E_INVALID;
+    for (int s = 0; s < 4; s++) if (p->bc[s] < 0 || p->bc[s] > BC_SOURCE) return ORC_E_INVALID;
+    if ((p->bc[0] == BC_PERIODIC) != (p->bc[1] == BC_PERIODIC)) return ORC_E_INVALID;
+    if ((p->bc[2] == BC_PERIODIC) != (p->bc[3] == BC_PERIODIC)) return ORC_E_INVALID;
+    return ORC_OK;
+}
+
+/* Largest |s^p| over every interface adjacent to an interior cell of the
+ * state, in both directions, with ghosts from the boundary rules at time t
+ * (the dry pass that fixes the first time step).  Returns -1 if a counted
+ * interface has non-real speeds. */
+double orc_dry_smax(const orc_params *p, const double *R, const double *M, const double *N, double t)
+{
+    if (check_params(p)) return -1.0;
+    work_t w;
+    if (work_alloc(&w, p->nx, p->ny)) { work_free(&w); return -1.0; }
+    for (int j = 0; j < p->ny; j++)
+        for (int i = 0; i < p->nx; i++) {
+            size_t d = idx(&w.a, i, j), s = (size_t)j * p->nx + i;
+            w.a.R[d] = R[s]; w.a.M[d] = M[s]; w.a.N[d] = N[s];
+        }
+    fill_ghosts_x(p, t, &w.a, 2);
+    fill_ghosts_y(p, t, &w.a, 2);
+    double smax = 0.0;
+    int bad = 0;
+    for (int j = 0; j < p->ny; j++)
+        for (int i = 0; i <= p->nx; i++) {
+            size_t l = idx(&w.a, i - 1, j), r = idx(&w.a, i, j);
+            double qL[3] = { w.a.R[l], w.a.M[l], w.a.N[l] }, qR[3] = { w.a.R[r], w.a.M[r], w.a.N[r] };
+            double s[3], rr[3][3], al[3], W[3][3], am[3], ap[3];
+            if (!orc_roe(p->beta, qL, qR, s, rr, al, W, am, ap)) { bad = 1; continue; }
+            for (int k = 0; k < 3; k++) { double a = fabs(s[k]); if (isnan(a) || a > smax) smax = a; }
+        }
+    for (int i = 0; i < p->nx; i++)
+        for (int j = 0; j <= p->ny; j++) {
+            size_t l = idx(&w.a, i, j - 1), r = idx(&w.a, i, j);
+            double qL[3] = { w.a.R[l], w.a.N[l], w.a.M[l] }, qR[3] = { w.a.R[r], w.a.N[r], w.a.M[r] };
+            double s[3], rr[3][3], al[3], W[3][3], am[3], ap[3];
+            if (!orc_roe(p->beta, qL, qR, s, rr, al, W, am, ap)) { bad = 1; continue; }
+            for (int k = 0; k < 3; k++) { double a = fabs(s[k]); if (isnan(a) || a > smax) smax = a; }
+        }
+    work_free(&w);
+    return bad ? -1.0 : smax;
+}
+
+/* Advance the state (R, M, N: row-major [ny][nx], x1 contiguous) by nsteps
+ * accepted steps.  *t is the time of the state; *dt the step to try next
+ * (<= 0: nu_W / smax of the dry pass).  CFL control (Sec. 4 opening): after
+ * each attempt nu = dt * smax; if nu > cfl_max the attempt is discarded and
+ * redone with dt * nu_W / nu (at most max_retries times in a row), otherwise
+ * it is accepted and the next step uses dt * nu_W / nu.  With fixed_dt the
+ * step is never changed and never rejected.  nu_hist (may be NULL) receives
+ * nu of each accepted step.  Returns ORC_OK or an error; on error the state
+ * holds the last accepted step. */
+int orc_run(const orc_params *p, double *R, double *M, double *N, long nsteps,
+            double *t, double *dt, orc_stats *st, double *nu_hist)
+{
+    int e = check_params(p);
+    if (e) return e;
+    memset(st, 0, sizeof(*st));
+    if (!(*dt > 0.0)) {
+        double s0 = orc_dry_smax(p, R, M, N, *t);
+        if (s0 < 0.0) { st->status = ORC_E_NONHYPERBOLIC; return ORC_E_NONHYPERBOLIC; }
+        if (!(s0 > 0.0) || !isfinite(s0)) { st->status = ORC_E_NONFINITE; return ORC_E_NONFINITE; }
+        *dt = p->cfl_target / s0;
+    }
+    work_t w;
+    if (work_alloc(&w, p->nx, p->ny)) { work_free(&w); return ORC_E_NOMEM; }
+    for (int j = 0; j < p->ny; j++)
+        for (int i = 0; i < p->nx; i++) {
+            size_t d = idx(&w.a, i, j), s = (size_t)j * p->nx + i;
+            w.a.R[d] = R[s]; w.a.M[d] = M[s]; w.a.N[d] = N[s];
+        }
+    double nu_mean = 0.0, nu_m2 = 0.0;    /* running mean and sum of squared deviations */
+    int retries = 0;
+    long accepted = 0;
+    e = ORC_OK;
+    while (accepted < nsteps) {
+        double smax;
+        int bad;
+        e = attempt(p, &w, *t, *dt, &smax, &bad);
+        if (e) break;
+        if (bad) { e = ORC_E_NONHYPERBOLIC; break; }
+        if (!isfinite(smax)) { e = ORC_E_NONFINITE; break; }
+        double nu = *dt * smax;
+        st->nu_last = nu;
+        if (!p->fixed_dt && nu > p->cfl_max) {
+            st->rejected++;
+            if (++retries > p->max_retries) { e = ORC_E_RETRIES; break; }
+            *dt = *dt * p->cfl_target / nu;
+            continue;
+        }
+        retries = 0;
+        for (int j = 0; j < p->ny; j++)
+            for (int i = 0; i < p->nx; i++) {
+                size_t d = idx(&w.a, i, j);
+                w.a.R[d] = w.d.R[d]; w.a.M[d] = w.d.M[d]; w.a.N[d] = w.d.N[d];
+            }
+        *t = *t + *dt;
+        if (nu_hist) nu_hist[accepted] = nu;
+        accepted++;
+        double dev = nu - nu_mean;
+        nu_mean = nu_mean + dev / (double)accepted;
+        nu_m2 = nu_m2 + dev * (nu - nu_mean);
+        if (!p->fixed_dt && smax > 0.0) *dt = *dt * p->cfl_target / nu;
+    }
+    for (int j = 0; j < p->ny; j++)
+        for (int i = 0; i < p->nx; i++) {
+            size_t d = idx(&w.a, i, j), s = (size_t)j * p->nx + i;
+            R[s] = w.a.R[d]; M[s] = w.a.M[d]; N[s] = w.a.N[d];
+        }
+    work_free(&w);
+    st->t = *t;
+    st->dt_next = *dt;
+    st->steps = accepted;
+    if (accepted > 0) {
+        st->nu_mean = nu_mean;
+        st->nu_std = sqrt(nu_m2 / (double)accepted);
+    }
+    st->status = e;
+    st->status_step = e ? accepted : 0;
+    return e;
+}
+
+/* Ghost value of the analytic Taylor profile and of the focused source, for
+ * the pins (exported so the tests can sample the boundary data directly). */
+void orc_taylor_value(const orc_params *p, double x, double y, double t, double q[3]) { taylor_value(p, x, y, t, q); }
+double orc_source_g(const orc_params *p, double r, double t) { return source_g(p, r, t); }

@@ -1,0 +1,142 @@
+"""Seeded synthetic workloads (initial conditions and SI parameters).
+
+This module holds no arithmetic of the finite-volume method: it only draws
+the seeded initial states and restates the five water-like workloads as plain
+dictionaries.  It is shared by the tests (which feed the same arrays to the
+HIP library and to the FP64 oracle) and by the benchmark.  Every random
+number comes from numpy's PCG64 (``numpy.random.default_rng``).
+
+Units are SI throughout: fields are (rho' [kg/m^3], rho*u [kg/m^2/s],
+rho*v [kg/m^2/s]) on a row-major [ny][nx] grid with x1 contiguous; cell (i, j)
+has its centre at ((i + 1/2) dx, (j + 1/2) dx).
+"""
+import numpy as np
+
+WATER = {"c0": 1500.0, "rho0": 1000.0, "beta": 3.5, "delta": 4.3e-6}
+
+
+def _medium(**over):
+    m = dict(WATER)
+    m.update(over)
+    return m
+
+
+def _p0(med):
+    return med["rho0"] * med["c0"] ** 2
+
+
+def taylor_step(nx=256, ny=256, dx=1e-4, amplitude_pa=1e6, x0_cells=64.0, noise=0.01,
+                seed=1, medium=None):
+    """Plane tanh pressure step of amplitude A (the jump is 2A) centred on a
+    cell face, right-going (momentum equal to rho0 c0 times the unperturbed
+    density ratio), with i.i.d. uniform multiplicative density noise
+    R <- R (1 + noise * xi), xi ~ U[-1, 1).  Returns (medium, rho_p, mx, my)."""
+    med = medium or _medium()
+    a = amplitude_pa / _p0(med)
+    width = (med["delta"] / med["c0"]) / (med["beta"] * a) / dx
+    x = np.arange(nx) + 0.5
+    R0 = -a * np.tanh((x - x0_cells) / width)
+    R0 = np.broadcast_to(R0, (ny, nx)).copy()
+    rng = np.random.default_rng(seed)
+    xi = rng.uniform(-1.0, 1.0, size=(ny, nx))
+    R = R0 * (1.0 + noise * xi)
+    rho_p = med["rho0"] * R
+    mx = med["rho0"] * med["c0"] * R0
+    my = np.zeros_like(R)
+    return med, rho_p, mx, my
+
+
+def gaussian_pulse(nx, ny, dx=1e-4, amplitude_pa=2e6, sigma_cells=20.0, noise=0.005, seed=2,
+                   centre_box=None, medium=None, rng=None):
+    """Gaussian density pulse R = a exp(-|x - xc|^2 / (2 sigma^2)) at rest, with
+    the centre drawn on a cell centre inside centre_box = ((i0, i1), (j0, j1))
+    (default: the middle half of the grid), plus additive white noise
+    noise * a * xi, xi ~ U[-1, 1) per cell.  Returns (medium, rho_p, mx, my, centre)."""
+    med = medium or _medium()
+    a = amplitude_pa / _p0(med)
+    rng = rng if rng is not None else np.random.default_rng(seed)
+    if centre_box is None:
+        centre_box = ((nx // 4, nx - nx // 4), (ny // 4, ny - ny // 4))
+    ci = int(rng.integers(centre_box[0][0], centre_box[0][1]))
+    cj = int(rng.integers(centre_box[1][0], centre_box[1][1]))
+    x = np.arange(nx) + 0.5
+    y = np.arange(ny) + 0.5
+    d2 = (x[None, :] - (ci + 0.5)) ** 2 + (y[:, None] - (cj + 0.5)) ** 2
+    R = a * np.exp(-d2 / (2.0 * sigma_cells ** 2))
+    if noise:
+        R = R + noise * a * rng.uniform(-1.0, 1.0, size=(ny, nx))
+    rho_p = med["rho0"] * R
+    return med, rho_p, np.zeros_like(R), np.zeros_like(R), (ci, cj)
+
+
+# --------------------------------------------------------------------------
+# The five workloads.  Each returns a dict with the SI parameters, the
+# boundary kinds per side (x-, x+, y-, y+), the step count and the initial
+# fields.  Grid sizes can be scaled down for tests with the keyword arguments.
+# --------------------------------------------------------------------------
+
+def c1_taylor_fp64(nx=256, ny=256, seed=1):
+    """Plain method, FP64: 256x256, dx = 1e-4 m, tanh step of 1 MPa at x = 64 dx,
+    1% noise, periodic in y, zero-order extrapolation in x, 200 adaptive steps."""
+    med, rp, mx, my = taylor_step(nx, ny, 1e-4, 1e6, 64.0 * nx / 256.0, 0.01, seed)
+    return {"name": "taylor-step 256x256 fp64", "nx": nx, "ny": ny, "dx": 1e-4, "medium": med,
+            "bc": ("extrap0", "extrap0", "periodic", "periodic"), "geometry": "planar",
+            "precision": "f64", "steps": 200, "cfl_target": 0.9, "cfl_max": 1.0,
+            "state": (rp, mx, my)}
+
+
+def c2_pulse_fp32(nx=4096, ny=4096, seed=2):
+    """FP32 Cartesian 4096^2: 2 MPa Gaussian (sigma 20 cells) at a seed-chosen
+    centre in [1536, 2560)^2 plus 0.5% white noise, absorbing (zero-order
+    extrapolation) sides, 2000 steps."""
+    box = ((nx * 3) // 8, (nx * 5) // 8), ((ny * 3) // 8, (ny * 5) // 8)
+    med, rp, mx, my, c = gaussian_pulse(nx, ny, 1e-4, 2e6, 20.0, 0.005, seed, centre_box=box)
+    return {"name": f"gaussian-pulse {nx}x{ny} fp32", "nx": nx, "ny": ny, "dx": 1e-4,
+            "medium": med, "bc": ("extrap0",) * 4, "geometry": "planar", "precision": "f32",
+            "steps": 2000, "cfl_target": 0.9, "cfl_max": 1.0, "state": (rp, mx, my),
+            "centre": c}
+
+
+def hifu_axisym(nz=8192, nr=2048, dx=2e-5, p_surface=2e5, steps=20000, precision="f32"):
+    """Axisymmetric (x1 = z, x2 = r) focused field: 1 MHz sinusoid on the z = 0
+    plane over r <= 35 mm with the paraxial focusing delay of a 62.6 mm focal
+    length, 3-cycle ramp, symmetry axis at r = 0, quiescent start."""
+    med = _medium()
+    z = np.zeros((nr, nz))
+    src = {"freq": 1e6, "p_surface": p_surface, "focal_length": 62.6e-3, "aperture": 35e-3,
+           "ramp_cycles": 3.0}
+    return {"name": f"hifu-axisym {nz}x{nr}", "nx": nz, "ny": nr, "dx": dx, "medium": med,
+            "bc": ("source", "extrap0", "reflect", "extrap0"), "geometry": "axisym",
+            "precision": precision, "steps": steps, "cfl_target": 0.9, "cfl_max": 1.0,
+            "source": src, "state": (z, z.copy(), z.copy())}
+
+
+def c3_hifu_fp32():
+    return hifu_axisym(8192, 2048, 2e-5, 2e5, 20000, "f32")
+
+
+def c5_hifu_mixed(precision="f32_f16store"):
+    return hifu_axisym(16384, 8192, 1e-5, 1e6, 40000, precision)
+
+
+def c4_batch(n=64, seed=4, size_range=(256, 2048), steps=1000):
+    """64 independent Cartesian simulations with seed-drawn uneven grids,
+    amplitude U(0.1, 5) MPa, beta U(3, 5), delta log-uniform in [1e-6, 1e-5]
+    m^2/s, Gaussian pulse (sigma 20 cells, no noise) in the middle half,
+    dx = 1e-4 m, extrapolating sides, per-simulation adaptive dt."""
+    children = np.random.SeedSequence(seed).spawn(n)
+    sims = []
+    for k, ss in enumerate(children):
+        rng = np.random.default_rng(ss)
+        nx = int(rng.integers(size_range[0], size_range[1] + 1))
+        ny = int(rng.integers(size_range[0], size_range[1] + 1))
+        amp = float(rng.uniform(0.1e6, 5e6))
+        beta = float(rng.uniform(3.0, 5.0))
+        delta = float(10.0 ** rng.uniform(-6.0, -5.0))
+        med = _medium(beta=beta, delta=delta)
+        med, rp, mx, my, c = gaussian_pulse(nx, ny, 1e-4, amp, 20.0, 0.0, medium=med, rng=rng)
+        sims.append({"name": f"batch-{k} {nx}x{ny}", "nx": nx, "ny": ny, "dx": 1e-4,
+                     "medium": med, "bc": ("extrap0",) * 4, "geometry": "planar",
+                     "precision": "f32", "steps": steps, "cfl_target": 0.9, "cfl_max": 1.0,
+                     "state": (rp, mx, my)})
+    return sims
