@@ -1,0 +1,1110 @@
+// fvna_runtime.hip -- host runtime and C ABI of libfvna (declared in include/fvna.h).
+//
+// Responsibilities: validate parameters, convert SI to the dimensionless
+// variables of the paper's renormalisation with the mesh spacing as length
+// unit (Sec. 3, eqs. renorm and phi-tdelta), bind caller-owned device
+// buffers, launch the fused step kernel and the device-side time-step
+// controller, replay them from a captured HIP graph, and surface the device
+// status word at synchronisation.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cfloat>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/fvna.h"
+#include "fvna_device.hpp"
+
+using namespace fvna;
+
+// ---------------------------------------------------------------------------
+// Kernels
+// ---------------------------------------------------------------------------
+
+template <typename S, typename T, int AXI>
+__global__ __launch_bounds__(256) void k_step(SimDesc d, int force)
+{
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tile = blockIdx.x * WAVES_PER_BLOCK + wave;
+    if (tile >= d.strips * d.segs) return;
+    const Clock* clk = d.clk;
+    if (!force && (clk->status != 0 || clk->accepted >= clk->target)) return;
+    march<S, T, AXI>(d, tile % d.strips, tile / d.strips, true);
+}
+
+struct TileRef { int sim, strip, seg, pad; };
+
+template <typename S, typename T, int AXI>
+__global__ __launch_bounds__(256) void k_step_batch(const SimDesc* __restrict__ descs,
+                                                    const TileRef* __restrict__ tiles, int ntiles,
+                                                    int force)
+{
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tile = blockIdx.x * WAVES_PER_BLOCK + wave;
+    if (tile >= ntiles) return;
+    const TileRef tr = tiles[tile];
+    const SimDesc d = descs[tr.sim];
+    const Clock* clk = d.clk;
+    if (!force && (clk->status != 0 || clk->accepted >= clk->target)) return;
+    march<S, T, AXI>(d, tr.strip, tr.seg, true);
+}
+
+// Accept or reject the attempt just made, from its largest wave speed
+// (CFL control of Sec. 4 opening; rejection rule as stated in include/fvna.h).
+__device__ void control(const SimDesc& d)
+{
+    Clock* c = d.clk;
+    if (c->status != 0 || c->accepted >= c->target) return;
+    c->attempts++;
+    const double smax = __longlong_as_double((long long)c->smax_bits);
+    const unsigned flags = c->flags;
+    c->smax_bits = 0ull;
+    c->flags = 0u;
+    if (flags & FLAG_NONHYP) { c->status = ST_NONHYP; c->status_step = c->accepted; return; }
+    if (!(smax <= DBL_MAX)) { c->status = ST_NONFINITE; c->status_step = c->accepted; return; }
+    const double nu = c->dt * smax;
+    c->nu_last = nu;
+    if (!d.fixed_dt && nu > d.cfl_max) {
+        c->rejected++;
+        if (++c->retries > d.max_retries) { c->status = ST_RETRIES; c->status_step = c->accepted; return; }
+        c->dt = c->dt * d.cfl_target / nu;
+        return;
+    }
+    c->retries = 0;
+    c->t = c->t + c->dt;
+    c->accepted++;
+    c->cur ^= 1;
+    c->nu_count++;
+    const double dev = nu - c->nu_mean;
+    c->nu_mean = c->nu_mean + dev / (double)c->nu_count;
+    c->nu_m2 = c->nu_m2 + dev * (nu - c->nu_mean);
+    if (!d.fixed_dt && smax > 0.0) c->dt = c->dt * d.cfl_target / nu;
+}
+
+__global__ void k_ctrl(SimDesc d)
+{
+    if (threadIdx.x == 0) control(d);
+}
+
+__global__ void k_ctrl_batch(const SimDesc* __restrict__ descs, int n)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) control(descs[k]);
+}
+
+__global__ void k_bump(Clock* c, long long n)
+{
+    if (threadIdx.x == 0) c->target += n;
+}
+
+__global__ void k_bump_batch(const SimDesc* __restrict__ descs, int n, long long steps)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) descs[k].clk->target += steps;
+}
+
+// Cell (i, j) of the state in buffer `cur`, with at most one index one step
+// outside the grid; ghost values follow the boundary rules at time t.
+template <typename S, typename T>
+__device__ Cell<T> cell_at(const SimDesc& d, int i, int j, double t)
+{
+    using C = Codec<S, T>;
+    const int nx = d.nx, ny = d.ny;
+    int si = i, sj = j;
+    T sgnM = T(1), sgnN = T(1);
+    int side = -1;
+    if (i < 0) side = 0;
+    else if (i >= nx) side = 1;
+    else if (j < 0) side = 2;
+    else if (j >= ny) side = 3;
+    if (side >= 0) {
+        const int b = d.bc[side];
+        if (b == BC_TAYLOR) {
+            double R, M, N;
+            taylor_at(d, i + 0.5, j + 0.5, t, R, M, N);
+            return Cell<T>{(T)R, (T)M, (T)N};
+        }
+        if (b == BC_SOURCE && (j + 0.5) <= d.sr_ap) {
+            Cell<T> q;
+            source_at<T>(d, j + 0.5, t, q.R, q.M, q.N);
+            return q;
+        }
+        if (b == BC_PERIODIC) {
+            if (side == 0) si = i + nx;
+            if (side == 1) si = i - nx;
+            if (side == 2) sj = j + ny;
+            if (side == 3) sj = j - ny;
+        } else if (b == BC_REFLECT) {
+            if (side == 0) { si = -1 - i; sgnM = T(-1); }
+            if (side == 1) { si = 2 * nx - 1 - i; sgnM = T(-1); }
+            if (side == 2) { sj = -1 - j; sgnN = T(-1); }
+            if (side == 3) { sj = 2 * ny - 1 - j; sgnN = T(-1); }
+        } else {
+            si = min(max(i, 0), nx - 1);
+            sj = min(max(j, 0), ny - 1);
+        }
+    }
+    const S* R = (const S*)d.buf[d.clk->cur];
+    const size_t o = (size_t)sj * (size_t)d.pitch + (size_t)si;
+    Cell<T> q;
+    q.R = C::ld(R[o], d.scale[0]);
+    q.M = sgnM * C::ld(R[d.plane + o], d.scale[1]);
+    q.N = sgnN * C::ld(R[2 * d.plane + o], d.scale[2]);
+    return q;
+}
+
+// Dry pass over every interface adjacent to an interior cell, both
+// directions: largest |s^p| of the current state (fixes the first step).
+template <typename S, typename T>
+__global__ __launch_bounds__(256) void k_dry(SimDesc d)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    const double t = d.clk->t;
+    const T beta = (T)d.beta;
+    T sm = T(0);
+    bool bad = false;
+    if (i <= d.nx) {
+        if (j < d.ny) {
+            const Cell<T> a = cell_at<S, T>(d, i - 1, j, t), b = cell_at<S, T>(d, i, j, t);
+            const T ia = rcp(T(1) + a.R), ib = rcp(T(1) + b.R);
+            Wave<T> w;
+            bad |= !roe(a.R, a.M, a.N, a.M * ia, a.N * ia, b.R, b.M, b.N, b.M * ib, b.N * ib, beta, w);
+            sm = max_(sm, max_(abs_(w.s1), max_(abs_(w.s2), abs_(w.s3))));
+        }
+        if (i < d.nx) {
+            const Cell<T> a = cell_at<S, T>(d, i, j - 1, t), b = cell_at<S, T>(d, i, j, t);
+            const T ia = rcp(T(1) + a.R), ib = rcp(T(1) + b.R);
+            Wave<T> w;
+            bad |= !roe(a.R, a.N, a.M, a.N * ia, a.M * ia, b.R, b.N, b.M, b.N * ib, b.M * ib, beta, w);
+            sm = max_(sm, max_(abs_(w.s1), max_(abs_(w.s2), abs_(w.s3))));
+        }
+    }
+    const int lane = threadIdx.x & 63;
+    for (int off = 32; off >= 1; off >>= 1) sm = max_(sm, perm(sm, lane ^ off));
+    const bool anybad = __any(bad);
+    if (lane == 0) {
+        atomicMax(&d.clk->smax_bits, (unsigned long long)__double_as_longlong((double)sm));
+        if (anybad) atomicOr(&d.clk->flags, (unsigned int)FLAG_NONHYP);
+    }
+}
+
+__global__ void k_dt0(SimDesc d)
+{
+    if (threadIdx.x != 0) return;
+    Clock* c = d.clk;
+    const double smax = __longlong_as_double((long long)c->smax_bits);
+    const unsigned flags = c->flags;
+    c->smax_bits = 0ull;
+    c->flags = 0u;
+    if (flags & FLAG_NONHYP) { c->status = ST_NONHYP; c->status_step = 0; return; }
+    if (!(smax > 0.0) || !(smax <= DBL_MAX)) { c->status = ST_NONFINITE; c->status_step = 0; return; }
+    c->dt = d.cfl_target / smax;
+}
+
+// Host doubles (SI, staged on the device) -> stored dimensionless field.
+template <typename S, typename T>
+__global__ void k_import(SimDesc d, const double* __restrict__ src, int field, int row0, int nrows,
+                         double denom, int buf)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (i >= d.pitch || r >= nrows) return;
+    S* dst = (S*)d.buf[buf] + (size_t)field * d.plane + (size_t)(row0 + r) * d.pitch;
+    const T v = (i < d.nx) ? (T)(src[(size_t)r * d.nx + i] / denom) : T(0);
+    dst[i] = Codec<S, T>::st(v, d.inv_scale[field]);
+}
+
+template <typename S, typename T>
+__global__ void k_export(SimDesc d, double* __restrict__ dst, int field, int row0, int nrows,
+                         double factor)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (i >= d.nx || r >= nrows) return;
+    const S* src = (const S*)d.buf[d.clk->cur] + (size_t)field * d.plane + (size_t)(row0 + r) * d.pitch;
+    dst[(size_t)r * d.nx + i] = (double)Codec<S, T>::ld(src[i], d.scale[field]) * factor;
+}
+
+// Fixed-order FP64 sums: block b sums rows b, b + NB, ... with a fixed
+// thread stride and a fixed tree; the final pass sums the NB partials.
+constexpr int SUM_BLOCKS = 512;
+
+template <typename S, typename T>
+__global__ __launch_bounds__(256) void k_sums_partial(SimDesc d, double* __restrict__ part)
+{
+    __shared__ double sh[3][256];
+    const int b = blockIdx.x;
+    double acc[3] = {0.0, 0.0, 0.0};
+    const S* base = (const S*)d.buf[d.clk->cur];
+    for (int j = b; j < d.ny; j += SUM_BLOCKS)
+        for (int i = threadIdx.x; i < d.nx; i += 256)
+            for (int f = 0; f < 3; ++f)
+                acc[f] += (double)Codec<S, T>::ld(base[(size_t)f * d.plane + (size_t)j * d.pitch + i], d.scale[f]);
+    for (int f = 0; f < 3; ++f) sh[f][threadIdx.x] = acc[f];
+    __syncthreads();
+    for (int s = 128; s >= 1; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int f = 0; f < 3; ++f) sh[f][threadIdx.x] += sh[f][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int f = 0; f < 3; ++f) part[(size_t)b * 3 + f] = sh[f][0];
+}
+
+__global__ __launch_bounds__(256) void k_sums_final(const double* __restrict__ part, double* __restrict__ out)
+{
+    __shared__ double sh[3][256];
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < SUM_BLOCKS; b += 256)
+        for (int f = 0; f < 3; ++f) acc[f] += part[(size_t)b * 3 + f];
+    for (int f = 0; f < 3; ++f) sh[f][threadIdx.x] = acc[f];
+    __syncthreads();
+    for (int s = 128; s >= 1; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int f = 0; f < 3; ++f) sh[f][threadIdx.x] += sh[f][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int f = 0; f < 3; ++f) out[f] = sh[f][0];
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+fvna_status fail(fvna_status s, const std::string& msg)
+{
+    g_err = msg;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(FVNA_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));    \
+    } while (0)
+
+constexpr size_t ALIGN = 256;
+constexpr size_t STAGE_CELLS = size_t(1) << 20;   // staging chunk for set/get state
+constexpr int GRAPH_CHUNK = 32;                   // attempts per captured graph
+
+constexpr size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+size_t elem_size(int precision)
+{
+    switch (precision) {
+    case FVNA_F64: return 8;
+    case FVNA_F32: return 4;
+    default: return 2;
+    }
+}
+
+int pitch_of(const fvna_params* p)
+{
+    // rows padded to a multiple of 256 bytes
+    const size_t es = elem_size(p->precision);
+    const size_t per = ALIGN / es;
+    return (int)align_up((size_t)p->nx, per);
+}
+
+fvna_status validate(const fvna_params* p)
+{
+    if (!p) return fail(FVNA_E_INVALID, "params is NULL");
+    if (p->nx < 4 || p->ny < 4) return fail(FVNA_E_INVALID, "grid must have at least 4 cells per axis");
+    if ((long long)p->nx * (long long)p->ny > (1ll << 34)) return fail(FVNA_E_INVALID, "grid too large");
+    if (!(p->dx > 0) || !(p->c0 > 0) || !(p->rho0 > 0))
+        return fail(FVNA_E_INVALID, "dx, c0 and rho0 must be positive");
+    if (!(p->beta >= 1.0)) return fail(FVNA_E_INVALID, "beta must be >= 1");
+    if (!(p->delta >= 0.0)) return fail(FVNA_E_INVALID, "delta must be >= 0");
+    if (p->geometry != FVNA_CARTESIAN && p->geometry != FVNA_AXISYMMETRIC)
+        return fail(FVNA_E_INVALID, "unknown geometry");
+    if (p->precision < FVNA_F64 || p->precision > FVNA_F32_BF16STORE)
+        return fail(FVNA_E_INVALID, "unknown precision");
+    if (!(p->cfl_target > 0.0) || !(p->cfl_target < p->cfl_max))
+        return fail(FVNA_E_INVALID, "need 0 < cfl_target < cfl_max");
+    if (p->max_retries < 0) return fail(FVNA_E_INVALID, "max_retries must be >= 0");
+    if (p->tile_rows != 0 && (p->tile_rows < 8 || p->tile_rows > 65536))
+        return fail(FVNA_E_INVALID, "tile_rows must be 0 or in [8, 65536]");
+    for (int s = 0; s < 4; ++s)
+        if (p->bc[s] < FVNA_BC_PERIODIC || p->bc[s] > FVNA_BC_SOURCE)
+            return fail(FVNA_E_INVALID, "unknown boundary kind");
+    if ((p->bc[0] == FVNA_BC_PERIODIC) != (p->bc[1] == FVNA_BC_PERIODIC) ||
+        (p->bc[2] == FVNA_BC_PERIODIC) != (p->bc[3] == FVNA_BC_PERIODIC))
+        return fail(FVNA_E_INVALID, "periodic must be set on both sides of an axis");
+    if (p->bc[1] == FVNA_BC_SOURCE || p->bc[2] == FVNA_BC_SOURCE || p->bc[3] == FVNA_BC_SOURCE)
+        return fail(FVNA_E_INVALID, "the focused source is only available on side x-");
+    if (p->geometry == FVNA_AXISYMMETRIC && p->bc[2] != FVNA_BC_REFLECT)
+        return fail(FVNA_E_INVALID, "axisymmetric geometry needs REFLECT on side y- (the axis)");
+    for (int f = 0; f < 3; ++f)
+        if (!(p->store_scale[f] >= 0.0)) return fail(FVNA_E_INVALID, "store_scale must be >= 0");
+    return FVNA_OK;
+}
+
+size_t state_bytes_of(const fvna_params* p)
+{
+    return align_up((size_t)3 * (size_t)pitch_of(p) * (size_t)p->ny * elem_size(p->precision), ALIGN);
+}
+
+// scratch layout: [Clock][sum partials][sum out][staging]
+constexpr size_t OFF_CLOCK = 0;
+constexpr size_t OFF_PART = 256;
+constexpr size_t OFF_SUMOUT = OFF_PART + align_up(SUM_BLOCKS * 3 * sizeof(double), ALIGN);
+constexpr size_t OFF_STAGE = OFF_SUMOUT + 256;
+
+size_t stage_cells_of(const fvna_params* p)
+{
+    const size_t cells = (size_t)p->nx * (size_t)p->ny;
+    return std::min(cells, std::max(STAGE_CELLS, (size_t)p->nx));
+}
+
+size_t scratch_bytes_of(const fvna_params* p)
+{
+    return OFF_STAGE + align_up(stage_cells_of(p) * sizeof(double), ALIGN);
+}
+
+int default_tile_rows(const fvna_params* p)
+{
+    (void)p;
+    return 64;
+}
+
+// in-process autotune cache keyed by (precision, geometry, nx, ny)
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int>, int> g_tune;
+
+}  // namespace
+
+struct Launcher {
+    void (*step)(const SimDesc&, int force, hipStream_t);
+    void (*step_batch)(const SimDesc*, const TileRef*, int ntiles, int force, hipStream_t);
+    void (*dry)(const SimDesc&, hipStream_t);
+    void (*imp)(const SimDesc&, const double*, int, int, int, double, int, hipStream_t);
+    void (*exp)(const SimDesc&, double*, int, int, int, double, hipStream_t);
+    void (*sums)(const SimDesc&, double*, hipStream_t);
+};
+
+template <typename S, typename T, int AXI>
+Launcher make_launcher()
+{
+    Launcher L;
+    L.step = [](const SimDesc& d, int force, hipStream_t s) {
+        const int tiles = d.strips * d.segs;
+        const int blocks = (tiles + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
+        hipLaunchKernelGGL((k_step<S, T, AXI>), dim3(blocks), dim3(256), 0, s, d, force);
+    };
+    L.step_batch = [](const SimDesc* descs, const TileRef* tiles, int ntiles, int force, hipStream_t s) {
+        const int blocks = (ntiles + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
+        hipLaunchKernelGGL((k_step_batch<S, T, AXI>), dim3(blocks), dim3(256), 0, s, descs, tiles, ntiles, force);
+    };
+    L.dry = [](const SimDesc& d, hipStream_t s) {
+        hipLaunchKernelGGL((k_dry<S, T>), dim3((d.nx + 1 + 255) / 256, d.ny + 1), dim3(256), 0, s, d);
+    };
+    L.imp = [](const SimDesc& d, const double* src, int field, int row0, int nrows, double denom, int buf,
+               hipStream_t s) {
+        hipLaunchKernelGGL((k_import<S, T>), dim3((d.pitch + 255) / 256, nrows), dim3(256), 0, s, d, src, field,
+                           row0, nrows, denom, buf);
+    };
+    L.exp = [](const SimDesc& d, double* dst, int field, int row0, int nrows, double factor, hipStream_t s) {
+        hipLaunchKernelGGL((k_export<S, T>), dim3((d.nx + 255) / 256, nrows), dim3(256), 0, s, d, dst, field, row0,
+                           nrows, factor);
+    };
+    L.sums = [](const SimDesc& d, double* part, hipStream_t s) {
+        hipLaunchKernelGGL((k_sums_partial<S, T>), dim3(SUM_BLOCKS), dim3(256), 0, s, d, part);
+        hipLaunchKernelGGL(k_sums_final, dim3(1), dim3(256), 0, s, part, part + SUM_BLOCKS * 3);
+    };
+    return L;
+}
+
+static Launcher pick_launcher(int precision, int geometry)
+{
+    const bool a = geometry == FVNA_AXISYMMETRIC;
+    switch (precision) {
+    case FVNA_F64: return a ? make_launcher<double, double, 1>() : make_launcher<double, double, 0>();
+    case FVNA_F32: return a ? make_launcher<float, float, 1>() : make_launcher<float, float, 0>();
+    case FVNA_F32_F16STORE: return a ? make_launcher<_Float16, float, 1>() : make_launcher<_Float16, float, 0>();
+    default: return a ? make_launcher<bf16, float, 1>() : make_launcher<bf16, float, 0>();
+    }
+}
+
+// Fill the simulation descriptor (everything dimensionless) from SI params.
+static void fill_desc(SimDesc& d, const fvna_params* p, void* a, void* b, Clock* clk, int tile_rows)
+{
+    std::memset(&d, 0, sizeof(d));
+    d.nx = p->nx;
+    d.ny = p->ny;
+    d.pitch = pitch_of(p);
+    d.plane = (long long)d.pitch * (long long)p->ny;
+    d.strips = (p->nx + OUTW - 1) / OUTW;
+    d.tile_rows = tile_rows;
+    d.segs = (p->ny + tile_rows - 1) / tile_rows;
+    for (int s = 0; s < 4; ++s) d.bc[s] = p->bc[s];
+    d.fixed_dt = p->fixed_dt ? 1 : 0;
+    d.max_retries = p->max_retries;
+    d.beta = p->beta;
+    d.delta = p->delta / (p->c0 * p->dx);
+    d.cfl_target = p->cfl_target;
+    d.cfl_max = p->cfl_max;
+    d.ta_amp = 0.0; d.ta_w = 1.0; d.ta_cos = 1.0; d.ta_sin = 0.0;
+    d.sr_freq = 1.0; d.sr_F = 1e30; d.sr_ramp = 3.0;
+    for (int f = 0; f < 3; ++f) {
+        const bool half = p->precision == FVNA_F32_F16STORE || p->precision == FVNA_F32_BF16STORE;
+        const double sc = (half && p->store_scale[f] > 0.0) ? p->store_scale[f] : 1.0;
+        d.scale[f] = (float)sc;
+        d.inv_scale[f] = (float)(1.0 / sc);
+    }
+    d.buf[0] = a;
+    d.buf[1] = b;
+    d.clk = clk;
+}
+
+struct fvna_ctx {
+    fvna_params p;
+    SimDesc d;
+    Launcher L;
+    hipStream_t stream;         // caller's stream (borrowed)
+    hipStream_t cap;            // private stream used only to capture graphs
+    char* scratch;
+    Clock* clk;
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    int device = 0;
+};
+
+static void drop_graph(fvna_ctx* c)
+{
+    if (c->exec) (void)hipGraphExecDestroy(c->exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->exec = nullptr;
+    c->graph = nullptr;
+}
+
+static fvna_status build_graph(fvna_ctx* c)
+{
+    if (c->exec) return FVNA_OK;
+    HIP_TRY(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < GRAPH_CHUNK; ++k) {
+        c->L.step(c->d, 0, c->cap);
+        hipLaunchKernelGGL(k_ctrl, dim3(1), dim3(64), 0, c->cap, c->d);
+    }
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamEndCapture(c->cap, &g));
+    c->graph = g;
+    HIP_TRY(hipGraphInstantiate(&c->exec, g, nullptr, nullptr, 0));
+    return FVNA_OK;
+}
+
+// Host copy of the clock.
+static fvna_status read_clock(fvna_ctx* c, Clock* h)
+{
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipMemcpy(h, c->clk, sizeof(Clock), hipMemcpyDeviceToHost));
+    return FVNA_OK;
+}
+
+static fvna_status status_of(int st)
+{
+    switch (st) {
+    case 0: return FVNA_OK;
+    case ST_NONHYP: return fail(FVNA_E_NONHYPERBOLIC, "non-real Roe speeds (discriminant <= 0) in a step");
+    case ST_NONFINITE: return fail(FVNA_E_NONFINITE, "non-finite wave speed in a step");
+    case ST_RETRIES: return fail(FVNA_E_RETRIES, "too many rejected attempts in a row");
+    default: return fail(FVNA_E_STATE, "unknown device status");
+    }
+}
+
+// Reset the clock to (t, dt) and recompute dt from the state if dt <= 0.
+static fvna_status reset_clock(fvna_ctx* c, double t_dimless, double dt_dimless, int cur)
+{
+    Clock h;
+    std::memset(&h, 0, sizeof(h));
+    h.t = t_dimless;
+    h.dt = dt_dimless > 0.0 ? dt_dimless : 0.0;
+    h.cur = cur;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipMemcpy(c->clk, &h, sizeof(Clock), hipMemcpyHostToDevice));
+    if (!(dt_dimless > 0.0)) {
+        c->L.dry(c->d, c->stream);
+        HIP_TRY(hipGetLastError());
+        hipLaunchKernelGGL(k_dt0, dim3(1), dim3(64), 0, c->stream, c->d);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipStreamSynchronize(c->stream));
+    }
+    return FVNA_OK;
+}
+
+extern "C" {
+
+fvna_status fvna_workspace_size(const fvna_params* p, size_t* state_bytes, size_t* scratch_bytes)
+{
+    fvna_status s = validate(p);
+    if (s) return s;
+    if (state_bytes) *state_bytes = state_bytes_of(p);
+    if (scratch_bytes) *scratch_bytes = scratch_bytes_of(p);
+    return FVNA_OK;
+}
+
+fvna_status fvna_create(const fvna_params* p, void* state_a, void* state_b, void* scratch, void* hip_stream,
+                        fvna_ctx** out)
+{
+    if (!out) return fail(FVNA_E_INVALID, "out is NULL");
+    *out = nullptr;
+    fvna_status s = validate(p);
+    if (s) return s;
+    if (!state_a || !state_b || !scratch) return fail(FVNA_E_INVALID, "device buffer is NULL");
+    if (((uintptr_t)state_a | (uintptr_t)state_b | (uintptr_t)scratch) % ALIGN)
+        return fail(FVNA_E_INVALID, "device buffers must be 256-byte aligned");
+    if (state_a == state_b) return fail(FVNA_E_INVALID, "state_a and state_b must differ");
+    fvna_ctx* c = new (std::nothrow) fvna_ctx();
+    if (!c) return fail(FVNA_E_NOMEM, "out of host memory");
+    c->p = *p;
+    c->stream = (hipStream_t)hip_stream;
+    c->scratch = (char*)scratch;
+    c->clk = (Clock*)(c->scratch + OFF_CLOCK);
+    c->L = pick_launcher(p->precision, p->geometry);
+    int tr = p->tile_rows;
+    if (tr == 0) {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        auto it = g_tune.find(std::make_tuple(p->precision, p->geometry, p->nx, p->ny));
+        tr = it != g_tune.end() ? it->second : default_tile_rows(p);
+    }
+    fill_desc(c->d, p, state_a, state_b, c->clk, tr);
+    if (hipGetDevice(&c->device) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess) {
+        delete c;
+        return fail(FVNA_E_HIP, "cannot create the capture stream");
+    }
+    // zero state, t = 0
+    const size_t sb = state_bytes_of(p);
+    if (hipMemsetAsync(state_a, 0, sb, c->stream) != hipSuccess ||
+        hipMemsetAsync(state_b, 0, sb, c->stream) != hipSuccess) {
+        (void)hipStreamDestroy(c->cap);
+        delete c;
+        return fail(FVNA_E_HIP, "cannot clear the state buffers");
+    }
+    s = reset_clock(c, 0.0, p->dt0 > 0 ? p->dt0 * p->c0 / p->dx : 0.0, 0);
+    if (s) {
+        (void)hipStreamDestroy(c->cap);
+        delete c;
+        return s;
+    }
+    *out = c;
+    return FVNA_OK;
+}
+
+fvna_status fvna_set_bc(fvna_ctx* c, int32_t side, int32_t bc)
+{
+    if (!c) return fail(FVNA_E_INVALID, "ctx is NULL");
+    if (side < 0 || side > 3) return fail(FVNA_E_INVALID, "side must be 0..3");
+    fvna_params q = c->p;
+    q.bc[side] = bc;
+    fvna_status s = validate(&q);
+    if (s) return s;
+    c->p = q;
+    c->d.bc[side] = bc;
+    drop_graph(c);
+    return FVNA_OK;
+}
+
+fvna_status fvna_set_source(fvna_ctx* c, int32_t side, const fvna_source* s)
+{
+    if (!c || !s) return fail(FVNA_E_INVALID, "NULL argument");
+    if (side != 0) return fail(FVNA_E_INVALID, "the focused source is only available on side x-");
+    if (!(s->freq > 0) || !(s->focal_length > 0) || !(s->aperture >= 0) || !(s->ramp_cycles > 0))
+        return fail(FVNA_E_INVALID, "need freq > 0, focal_length > 0, aperture >= 0, ramp_cycles > 0");
+    const fvna_params& p = c->p;
+    c->d.sr_amp = s->p_surface / (p.rho0 * p.c0 * p.c0);
+    c->d.sr_freq = s->freq * p.dx / p.c0;
+    c->d.sr_F = s->focal_length / p.dx;
+    c->d.sr_ap = s->aperture / p.dx;
+    c->d.sr_ramp = s->ramp_cycles;
+    drop_graph(c);
+    return FVNA_OK;
+}
+
+fvna_status fvna_set_taylor(fvna_ctx* c, double amplitude_pa, double x0_m, double angle)
+{
+    if (!c) return fail(FVNA_E_INVALID, "ctx is NULL");
+    const fvna_params& p = c->p;
+    if (!(amplitude_pa != 0.0) || !(p.delta > 0.0))
+        return fail(FVNA_E_INVALID, "the Taylor profile needs a non-zero amplitude and delta > 0");
+    const double a = amplitude_pa / (p.rho0 * p.c0 * p.c0);
+    c->d.ta_amp = a;
+    c->d.ta_w = (p.delta / p.c0) / (p.beta * a) / p.dx;
+    c->d.ta_x0 = x0_m / p.dx;
+    c->d.ta_y0 = 0.0;
+    c->d.ta_cos = std::cos(angle);
+    c->d.ta_sin = std::sin(angle);
+    drop_graph(c);
+    return FVNA_OK;
+}
+
+fvna_status fvna_set_state(fvna_ctx* c, const double* rho_p, const double* mom_x, const double* mom_y)
+{
+    if (!c || !rho_p || !mom_x || !mom_y) return fail(FVNA_E_INVALID, "NULL argument");
+    const fvna_params& p = c->p;
+    double* stage = (double*)(c->scratch + OFF_STAGE);
+    const size_t chunk_rows = std::max<size_t>(1, stage_cells_of(&p) / (size_t)p.nx);
+    const double denom[3] = {p.rho0, p.rho0 * p.c0, p.rho0 * p.c0};
+    const double* src[3] = {rho_p, mom_x, mom_y};
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    // the state goes into buffer 0; buffer 1 is cleared so padding stays zero
+    HIP_TRY(hipMemsetAsync(c->d.buf[1], 0, state_bytes_of(&p), c->stream));
+    for (int f = 0; f < 3; ++f)
+        for (size_t r0 = 0; r0 < (size_t)p.ny; r0 += chunk_rows) {
+            const size_t nr = std::min(chunk_rows, (size_t)p.ny - r0);
+            HIP_TRY(hipMemcpyAsync(stage, src[f] + r0 * (size_t)p.nx, nr * (size_t)p.nx * sizeof(double),
+                                   hipMemcpyHostToDevice, c->stream));
+            c->L.imp(c->d, stage, f, (int)r0, (int)nr, denom[f], 0, c->stream);
+            HIP_TRY(hipGetLastError());
+            HIP_TRY(hipStreamSynchronize(c->stream));
+        }
+    return reset_clock(c, 0.0, p.dt0 > 0 ? p.dt0 * p.c0 / p.dx : 0.0, 0);
+}
+
+fvna_status fvna_set_clock(fvna_ctx* c, double t, double dt_next)
+{
+    if (!c) return fail(FVNA_E_INVALID, "ctx is NULL");
+    Clock h;
+    fvna_status s = read_clock(c, &h);
+    if (s) return s;
+    const fvna_params& p = c->p;
+    return reset_clock(c, t * p.c0 / p.dx, dt_next > 0 ? dt_next * p.c0 / p.dx : 0.0, h.cur);
+}
+
+fvna_status fvna_step(fvna_ctx* c, int64_t nsteps)
+{
+    if (!c) return fail(FVNA_E_INVALID, "ctx is NULL");
+    if (nsteps < 0) return fail(FVNA_E_INVALID, "nsteps must be >= 0");
+    if (nsteps == 0) return FVNA_OK;
+    fvna_status s = build_graph(c);
+    if (s) return s;
+    hipLaunchKernelGGL(k_bump, dim3(1), dim3(64), 0, c->stream, c->clk, (long long)nsteps);
+    HIP_TRY(hipGetLastError());
+    const int64_t launches = (nsteps + GRAPH_CHUNK - 1) / GRAPH_CHUNK;
+    for (int64_t k = 0; k < launches; ++k) HIP_TRY(hipGraphLaunch(c->exec, c->stream));
+    return FVNA_OK;
+}
+
+fvna_status fvna_sync(fvna_ctx* c)
+{
+    if (!c) return fail(FVNA_E_INVALID, "ctx is NULL");
+    Clock h;
+    for (int guard = 0; guard < 1000; ++guard) {
+        fvna_status s = read_clock(c, &h);
+        if (s) return s;
+        if (h.status != 0 || h.accepted >= h.target) return status_of(h.status);
+        // rejected attempts left steps owed: run more attempts
+        const long long owed = h.target - h.accepted;
+        s = build_graph(c);
+        if (s) return s;
+        const long long launches = (owed + GRAPH_CHUNK - 1) / GRAPH_CHUNK;
+        for (long long k = 0; k < launches; ++k) HIP_TRY(hipGraphLaunch(c->exec, c->stream));
+    }
+    return fail(FVNA_E_STATE, "steps still owed after many top-up rounds");
+}
+
+// Copy the current state of a context out (no synchronisation of owed steps).
+static fvna_status export_state(fvna_ctx* c, double* rho_p, double* mom_x, double* mom_y)
+{
+    const fvna_params& p = c->p;
+    double* stage = (double*)(c->scratch + OFF_STAGE);
+    const size_t chunk_rows = std::max<size_t>(1, stage_cells_of(&p) / (size_t)p.nx);
+    const double factor[3] = {p.rho0, p.rho0 * p.c0, p.rho0 * p.c0};
+    double* dst[3] = {rho_p, mom_x, mom_y};
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (int f = 0; f < 3; ++f)
+        for (size_t r0 = 0; r0 < (size_t)p.ny; r0 += chunk_rows) {
+            const size_t nr = std::min(chunk_rows, (size_t)p.ny - r0);
+            c->L.exp(c->d, stage, f, (int)r0, (int)nr, factor[f], c->stream);
+            HIP_TRY(hipGetLastError());
+            HIP_TRY(hipMemcpyAsync(dst[f] + r0 * (size_t)p.nx, stage, nr * (size_t)p.nx * sizeof(double),
+                                   hipMemcpyDeviceToHost, c->stream));
+            HIP_TRY(hipStreamSynchronize(c->stream));
+        }
+    return FVNA_OK;
+}
+
+static fvna_status stats_of(fvna_ctx* c, fvna_stats* st)
+{
+    Clock h;
+    fvna_status r = read_clock(c, &h);
+    if (r) return r;
+    const double tu = c->p.dx / c->p.c0;
+    st->t = h.t * tu;
+    st->dt_next = h.dt * tu;
+    st->nu_last = h.nu_last;
+    st->nu_mean = h.nu_mean;
+    st->nu_std = h.nu_count > 0 ? std::sqrt(h.nu_m2 / (double)h.nu_count) : 0.0;
+    st->steps = h.accepted;
+    st->rejected = h.rejected;
+    st->status = h.status;
+    st->status_step = h.status_step;
+    return FVNA_OK;
+}
+
+static bool is_device_error(fvna_status s)
+{
+    return s == FVNA_E_NONHYPERBOLIC || s == FVNA_E_NONFINITE || s == FVNA_E_RETRIES;
+}
+
+fvna_status fvna_get_state(fvna_ctx* c, double* rho_p, double* mom_x, double* mom_y)
+{
+    if (!c || !rho_p || !mom_x || !mom_y) return fail(FVNA_E_INVALID, "NULL argument");
+    const fvna_status dev = fvna_sync(c);
+    if (dev != FVNA_OK && !is_device_error(dev)) return dev;
+    const std::string msg = g_err;
+    fvna_status s = export_state(c, rho_p, mom_x, mom_y);
+    if (s) return s;
+    if (dev != FVNA_OK) g_err = msg;
+    return dev;
+}
+
+fvna_status fvna_get_stats(fvna_ctx* c, fvna_stats* st)
+{
+    if (!c || !st) return fail(FVNA_E_INVALID, "NULL argument");
+    const fvna_status dev = fvna_sync(c);
+    if (dev != FVNA_OK && !is_device_error(dev)) return dev;
+    const std::string msg = g_err;
+    fvna_status s = stats_of(c, st);
+    if (s) return s;
+    if (dev != FVNA_OK) g_err = msg;
+    return dev;
+}
+
+fvna_status fvna_sums(fvna_ctx* c, double out[3])
+{
+    if (!c || !out) return fail(FVNA_E_INVALID, "NULL argument");
+    fvna_status s = fvna_sync(c);
+    if (s != FVNA_OK && !is_device_error(s)) return s;
+    double* part = (double*)(c->scratch + OFF_PART);
+    c->L.sums(c->d, part, c->stream);
+    HIP_TRY(hipGetLastError());
+    double h[3];
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipMemcpy(h, c->scratch + OFF_SUMOUT, sizeof(h), hipMemcpyDeviceToHost));
+    const fvna_params& p = c->p;
+    out[0] = h[0] * p.rho0;
+    out[1] = h[1] * p.rho0 * p.c0;
+    out[2] = h[2] * p.rho0 * p.c0;
+    return FVNA_OK;
+}
+
+fvna_status fvna_time_step_kernel(fvna_ctx* c, int32_t reps, double* ms_per_launch)
+{
+    if (!c || !ms_per_launch || reps < 1) return fail(FVNA_E_INVALID, "bad argument");
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(hipEventRecord(e0, c->stream));
+    for (int k = 0; k < reps; ++k) c->L.step(c->d, 1, c->stream);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipEventRecord(e1, c->stream));
+    HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms_per_launch = (double)ms / reps;
+    return FVNA_OK;
+}
+
+fvna_status fvna_get_tile_rows(fvna_ctx* c, int32_t* tile_rows)
+{
+    if (!c || !tile_rows) return fail(FVNA_E_INVALID, "NULL argument");
+    *tile_rows = c->d.tile_rows;
+    return FVNA_OK;
+}
+
+fvna_status fvna_autotune(fvna_ctx* c, int32_t* tile_rows)
+{
+    if (!c) return fail(FVNA_E_INVALID, "ctx is NULL");
+    static const int cand[] = {16, 24, 32, 48, 64, 96, 128, 192, 256};
+    double best = 1e30;
+    int best_tr = c->d.tile_rows;
+    for (int tr : cand) {
+        if (tr > 2 * c->p.ny) continue;
+        c->d.tile_rows = tr;
+        c->d.segs = (c->p.ny + tr - 1) / tr;
+        double ms = 0.0;
+        fvna_status s = fvna_time_step_kernel(c, 1, &ms);       // warm-up
+        if (!s) s = fvna_time_step_kernel(c, 5, &ms);
+        if (s) return s;
+        if (ms < best) { best = ms; best_tr = tr; }
+    }
+    c->d.tile_rows = best_tr;
+    c->d.segs = (c->p.ny + best_tr - 1) / best_tr;
+    // the timing launches left this attempt's speeds in the clock; they are
+    // exactly what the next real attempt computes, so nothing to undo
+    drop_graph(c);
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        g_tune[std::make_tuple(c->p.precision, c->p.geometry, c->p.nx, c->p.ny)] = best_tr;
+    }
+    if (tile_rows) *tile_rows = best_tr;
+    return FVNA_OK;
+}
+
+const char* fvna_last_error(void) { return g_err.c_str(); }
+
+void fvna_destroy(fvna_ctx* c)
+{
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    drop_graph(c);
+    (void)hipStreamDestroy(c->cap);
+    delete c;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched form
+// ---------------------------------------------------------------------------
+
+struct fvna_batch {
+    int n = 0;
+    std::vector<fvna_params> p;
+    std::vector<SimDesc> d;
+    std::vector<char*> scratch;
+    Launcher L;
+    hipStream_t stream;
+    hipStream_t cap;
+    SimDesc* d_desc = nullptr;      // device copy of the descriptors
+    TileRef* d_tiles = nullptr;
+    int ntiles = 0;
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+};
+
+static fvna_status batch_graph(fvna_batch* b)
+{
+    if (b->exec) return FVNA_OK;
+    HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < GRAPH_CHUNK; ++k) {
+        b->L.step_batch(b->d_desc, b->d_tiles, b->ntiles, 0, b->cap);
+        hipLaunchKernelGGL(k_ctrl_batch, dim3((b->n + 63) / 64), dim3(64), 0, b->cap, b->d_desc, b->n);
+    }
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamEndCapture(b->cap, &g));
+    b->graph = g;
+    HIP_TRY(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0));
+    return FVNA_OK;
+}
+
+// A batch member seen as a single context (shares kernels and conversions).
+static fvna_ctx member_ctx(fvna_batch* b, int k)
+{
+    fvna_ctx c;
+    c.p = b->p[k];
+    c.d = b->d[k];
+    c.L = b->L;
+    c.stream = b->stream;
+    c.cap = b->cap;
+    c.scratch = b->scratch[k];
+    c.clk = (Clock*)(b->scratch[k] + OFF_CLOCK);
+    return c;
+}
+
+extern "C" {
+
+fvna_status fvna_batch_create(int32_t n, const fvna_params* per_sim, void* const* bufs, void* hip_stream,
+                              fvna_batch** out)
+{
+    if (!out || !per_sim || !bufs || n < 1) return fail(FVNA_E_INVALID, "bad argument");
+    *out = nullptr;
+    for (int k = 0; k < n; ++k) {
+        fvna_status s = validate(&per_sim[k]);
+        if (s) return fail(s, "simulation " + std::to_string(k) + ": " + g_err);
+        if (per_sim[k].precision != per_sim[0].precision || per_sim[k].geometry != per_sim[0].geometry)
+            return fail(FVNA_E_INVALID, "all simulations of a batch need the same precision and geometry");
+        for (int j = 0; j < 3; ++j)
+            if (!bufs[3 * k + j] || ((uintptr_t)bufs[3 * k + j]) % ALIGN)
+                return fail(FVNA_E_INVALID, "device buffers must be non-NULL and 256-byte aligned");
+    }
+    fvna_batch* b = new (std::nothrow) fvna_batch();
+    if (!b) return fail(FVNA_E_NOMEM, "out of host memory");
+    b->n = n;
+    b->stream = (hipStream_t)hip_stream;
+    b->L = pick_launcher(per_sim[0].precision, per_sim[0].geometry);
+    std::vector<TileRef> tiles;
+    for (int k = 0; k < n; ++k) {
+        const fvna_params& p = per_sim[k];
+        b->p.push_back(p);
+        SimDesc d;
+        int tr = p.tile_rows ? p.tile_rows : default_tile_rows(&p);
+        char* sc = (char*)bufs[3 * k + 2];
+        fill_desc(d, &p, bufs[3 * k], bufs[3 * k + 1], (Clock*)(sc + OFF_CLOCK), tr);
+        b->d.push_back(d);
+        b->scratch.push_back(sc);
+        for (int sg = 0; sg < d.segs; ++sg)
+            for (int st = 0; st < d.strips; ++st) tiles.push_back(TileRef{k, st, sg, 0});
+    }
+    b->ntiles = (int)tiles.size();
+    auto cleanup = [&]() {
+        if (b->d_desc) (void)hipFree(b->d_desc);
+        if (b->d_tiles) (void)hipFree(b->d_tiles);
+        delete b;
+    };
+    if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
+        delete b;
+        return fail(FVNA_E_HIP, "cannot create the capture stream");
+    }
+    if (hipMalloc(&b->d_desc, sizeof(SimDesc) * n) != hipSuccess ||
+        hipMalloc(&b->d_tiles, sizeof(TileRef) * tiles.size()) != hipSuccess) {
+        (void)hipStreamDestroy(b->cap);
+        cleanup();
+        return fail(FVNA_E_HIP, "cannot allocate the batch tables");
+    }
+    if (hipMemcpy(b->d_desc, b->d.data(), sizeof(SimDesc) * n, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->d_tiles, tiles.data(), sizeof(TileRef) * tiles.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipStreamDestroy(b->cap);
+        cleanup();
+        return fail(FVNA_E_HIP, "cannot upload the batch tables");
+    }
+    for (int k = 0; k < n; ++k) {
+        fvna_ctx c = member_ctx(b, k);
+        const fvna_params& p = per_sim[k];
+        const size_t sb = state_bytes_of(&p);
+        if (hipMemsetAsync(c.d.buf[0], 0, sb, b->stream) != hipSuccess ||
+            hipMemsetAsync(c.d.buf[1], 0, sb, b->stream) != hipSuccess ||
+            reset_clock(&c, 0.0, p.dt0 > 0 ? p.dt0 * p.c0 / p.dx : 0.0, 0) != FVNA_OK) {
+            (void)hipStreamDestroy(b->cap);
+            cleanup();
+            return fail(FVNA_E_HIP, "cannot initialise simulation " + std::to_string(k));
+        }
+    }
+    *out = b;
+    return FVNA_OK;
+}
+
+fvna_status fvna_batch_set_state(fvna_batch* b, int32_t k, const double* rho_p, const double* mom_x,
+                                 const double* mom_y)
+{
+    if (!b || k < 0 || k >= b->n) return fail(FVNA_E_INVALID, "bad simulation index");
+    fvna_ctx c = member_ctx(b, k);
+    return fvna_set_state(&c, rho_p, mom_x, mom_y);
+}
+
+fvna_status fvna_batch_step(fvna_batch* b, int64_t nsteps)
+{
+    if (!b) return fail(FVNA_E_INVALID, "batch is NULL");
+    if (nsteps < 0) return fail(FVNA_E_INVALID, "nsteps must be >= 0");
+    if (nsteps == 0) return FVNA_OK;
+    fvna_status s = batch_graph(b);
+    if (s) return s;
+    hipLaunchKernelGGL(k_bump_batch, dim3((b->n + 63) / 64), dim3(64), 0, b->stream, b->d_desc, b->n,
+                       (long long)nsteps);
+    HIP_TRY(hipGetLastError());
+    const int64_t launches = (nsteps + GRAPH_CHUNK - 1) / GRAPH_CHUNK;
+    for (int64_t k = 0; k < launches; ++k) HIP_TRY(hipGraphLaunch(b->exec, b->stream));
+    return FVNA_OK;
+}
+
+fvna_status fvna_batch_sync(fvna_batch* b)
+{
+    if (!b) return fail(FVNA_E_INVALID, "batch is NULL");
+    for (int guard = 0; guard < 1000; ++guard) {
+        HIP_TRY(hipStreamSynchronize(b->stream));
+        long long owed = 0;
+        int worst = 0;
+        for (int k = 0; k < b->n; ++k) {
+            Clock h;
+            HIP_TRY(hipMemcpy(&h, b->scratch[k] + OFF_CLOCK, sizeof(Clock), hipMemcpyDeviceToHost));
+            if (h.status) worst = worst ? worst : h.status;
+            else owed = std::max(owed, h.target - h.accepted);
+        }
+        if (owed <= 0) return status_of(worst);
+        fvna_status s = batch_graph(b);
+        if (s) return s;
+        const long long launches = (owed + GRAPH_CHUNK - 1) / GRAPH_CHUNK;
+        for (long long k = 0; k < launches; ++k) HIP_TRY(hipGraphLaunch(b->exec, b->stream));
+    }
+    return fail(FVNA_E_STATE, "steps still owed after many top-up rounds");
+}
+
+// Device status of one member, as a status code (message set).
+static fvna_status member_status(fvna_ctx* c)
+{
+    Clock h;
+    fvna_status r = read_clock(c, &h);
+    if (r) return r;
+    return status_of(h.status);
+}
+
+fvna_status fvna_batch_get_state(fvna_batch* b, int32_t k, double* rho_p, double* mom_x, double* mom_y)
+{
+    if (!b || k < 0 || k >= b->n || !rho_p || !mom_x || !mom_y) return fail(FVNA_E_INVALID, "bad argument");
+    const fvna_status bs = fvna_batch_sync(b);
+    if (bs != FVNA_OK && !is_device_error(bs)) return bs;
+    fvna_ctx c = member_ctx(b, k);
+    const fvna_status dev = member_status(&c);
+    if (dev != FVNA_OK && !is_device_error(dev)) return dev;
+    const std::string msg = g_err;
+    fvna_status s = export_state(&c, rho_p, mom_x, mom_y);
+    if (s) return s;
+    if (dev != FVNA_OK) g_err = msg;
+    return dev;
+}
+
+fvna_status fvna_batch_get_stats(fvna_batch* b, int32_t k, fvna_stats* st)
+{
+    if (!b || k < 0 || k >= b->n || !st) return fail(FVNA_E_INVALID, "bad argument");
+    const fvna_status bs = fvna_batch_sync(b);
+    if (bs != FVNA_OK && !is_device_error(bs)) return bs;
+    fvna_ctx c = member_ctx(b, k);
+    const fvna_status dev = member_status(&c);
+    if (dev != FVNA_OK && !is_device_error(dev)) return dev;
+    const std::string msg = g_err;
+    fvna_status s = stats_of(&c, st);
+    if (s) return s;
+    if (dev != FVNA_OK) g_err = msg;
+    return dev;
+}
+
+fvna_status fvna_batch_time_step_kernel(fvna_batch* b, int32_t reps, double* ms_per_launch)
+{
+    if (!b || !ms_per_launch || reps < 1) return fail(FVNA_E_INVALID, "bad argument");
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(hipEventRecord(e0, b->stream));
+    for (int k = 0; k < reps; ++k) b->L.step_batch(b->d_desc, b->d_tiles, b->ntiles, 1, b->stream);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipEventRecord(e1, b->stream));
+    HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms_per_launch = (double)ms / reps;
+    return FVNA_OK;
+}
+
+void fvna_batch_destroy(fvna_batch* b)
+{
+    if (!b) return;
+    (void)hipStreamSynchronize(b->stream);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    (void)hipStreamDestroy(b->cap);
+    (void)hipFree(b->d_desc);
+    (void)hipFree(b->d_tiles);
+    delete b;
+}
+
+}  // extern "C"

@@ -1,0 +1,78 @@
+"""The C-ABI library loads and exports every entry point include/fvna.h
+declares; parameter validation works without a GPU (no compute calls)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fvna.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fvna_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def fv():
+    from paper_1311_3004_amd import build as b
+    if b.stale():
+        b.build()
+    from paper_1311_3004_amd import fvna
+    return fvna
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("fvna_create", "fvna_step", "fvna_get_state", "fvna_set_bc", "fvna_set_source",
+                     "fvna_batch_create", "fvna_batch_step"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(fv):
+    L = ctypes.CDLL(fv.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+    assert sorted(fv.EXPORTS) == declared_functions()
+
+
+MED = {"c0": 1500.0, "rho0": 1000.0, "beta": 3.5, "delta": 4.3e-6}
+
+
+def test_workspace_sizes(fv):
+    p = fv.make_params(4096, 4096, 1e-4, MED, precision="f32")
+    sb, xb = fv.workspace_size(p)
+    assert sb == 3 * 4096 * 4096 * 4
+    p = fv.make_params(1000, 10, 1e-4, MED, precision="f64")
+    sb, _ = fv.workspace_size(p)
+    assert sb % 256 == 0 and sb >= 3 * 1000 * 10 * 8
+    p = fv.make_params(1000, 10, 1e-4, MED, precision="f32_f16store")
+    sb16, _ = fv.workspace_size(p)
+    assert sb16 * 4 == sb or sb16 >= 3 * 1000 * 10 * 2
+
+
+@pytest.mark.parametrize("over,msg", [
+    (dict(nx=3), "at least 4"),
+    (dict(cfl_target=1.0), "cfl_target"),
+    (dict(cfl_target=1.2, cfl_max=1.0), "cfl_target"),
+    (dict(beta=0.5), "beta"),
+    (dict(delta=-1.0), "delta"),
+    (dict(dx=0.0), "positive"),
+    (dict(bc=("periodic", "extrap0", "extrap0", "extrap0")), "periodic"),
+    (dict(bc=("extrap0", "source", "extrap0", "extrap0")), "source"),
+    (dict(geometry="axisym", bc=("extrap0",) * 4), "axis"),
+    (dict(tile_rows=4), "tile_rows"),
+])
+def test_invalid_parameters_rejected(fv, over, msg):
+    kw = dict(nx=64, ny=64, dx=1e-4, bc=("extrap0",) * 4, cfl_target=0.9, cfl_max=1.0, beta=3.5,
+              delta=4.3e-6, geometry="planar", tile_rows=0)
+    kw.update(over)
+    med = dict(MED, beta=kw.pop("beta"), delta=kw.pop("delta"))
+    p = fv.make_params(kw.pop("nx"), kw.pop("ny"), kw.pop("dx"), med, **kw)
+    with pytest.raises(fv.FvnaError) as e:
+        fv.workspace_size(p)
+    assert e.value.status == fv.E_INVALID
+    assert msg in str(e.value)

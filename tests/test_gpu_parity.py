@@ -1,0 +1,239 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances: FP64 GPU vs oracle, max |difference| over the three fields
+relative to the peak |rho'/rho0|: 1e-12 with a fixed time step, 1e-10 with
+the adaptive step (the step sizes then differ in the last bits too).  The two
+sides round differently (FMA, operation order), nothing else.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from common import max_rel, pulse_workload, run_gpu, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1311_3004_amd import fvna  # noqa: F401  (fails loudly without the library)
+    yield
+
+
+def test_taylor_step_256_fp64_adaptive(orc):
+    """The plain-method workload in full: 256x256, 200 adaptive steps."""
+    from paper_1311_3004_amd import inputs
+    w = inputs.c1_taylor_fp64()
+    _say("case: taylor-step 256x256 fp64 adaptive 200 steps")
+    g, st, sim = run_gpu(w, 200, "f64")
+    o, info = run_oracle(orc, w, 200)
+    assert st["status"] == 0 and info["status"] == 0
+    assert st["steps"] == 200 and st["rejected"] == 0
+    err = max_rel(g, o)
+    _say(f"  max rel err {err:.3e}")
+    assert err <= 1e-10
+    c0, dx = w["medium"]["c0"], w["dx"]
+    assert abs(st["t"] * c0 / dx - info["t"]) <= 1e-12 * info["t"]
+    assert abs(st["nu_mean"] - info["nu_mean"]) <= 1e-12
+    sim.fvna_destroy()
+
+
+BC_CASES = {
+    "periodic": ("periodic", "periodic", "periodic", "periodic"),
+    "extrap0": ("extrap0",) * 4,
+    "reflect": ("reflect",) * 4,
+    "reflect-x-periodic-y": ("reflect", "reflect", "periodic", "periodic"),
+    "mixed": ("extrap0", "reflect", "reflect", "extrap0"),
+}
+
+
+@pytest.mark.parametrize("name", list(BC_CASES))
+@pytest.mark.parametrize("shape,tile", [((131, 77), 16), ((64, 40), 8), ((200, 130), 64)])
+def test_boundary_kinds_fixed_dt(orc, name, shape, tile):
+    nx, ny = shape
+    w = pulse_workload(nx, ny, BC_CASES[name], seed=nx + ny)
+    dt_si = 0.8 * w["dx"] / w["medium"]["c0"]
+    _say(f"case: bc={name} {nx}x{ny} tile={tile} fp64 fixed dt")
+    g, st, sim = run_gpu(w, 25, "f64", fixed_dt=True, dt_si=dt_si, tile_rows=tile)
+    o, info = run_oracle(orc, w, 25, fixed_dt=True, dt_si=dt_si)
+    assert st["status"] == 0 and info["status"] == 0
+    err = max_rel(g, o)
+    _say(f"  max rel err {err:.3e}")
+    assert err <= 1e-12
+    assert abs(st["nu_mean"] - info["nu_mean"]) <= 1e-13
+    sim.fvna_destroy()
+
+
+def test_taylor_boundaries(orc):
+    """Dirichlet Taylor data on both x ends, periodic rows (Sec. 4.1 set-up)."""
+    from paper_1311_3004_amd import inputs
+    nx, ny = 150, 8
+    med = dict(inputs.WATER)
+    dx = 2e-6
+    A = 2e6
+    a = A / (med["rho0"] * med["c0"] ** 2)
+    width = (med["delta"] / med["c0"]) / (med["beta"] * a) / dx
+    x = np.arange(nx) + 0.5
+    x0 = 40.0
+    R0 = np.broadcast_to(-a * np.tanh((x - x0) / width), (ny, nx)).copy()
+    w = {"nx": nx, "ny": ny, "dx": dx, "medium": med, "bc": ("taylor", "taylor", "periodic", "periodic"),
+         "geometry": "planar", "precision": "f64",
+         "taylor": {"amplitude_pa": A, "x0_m": x0 * dx, "angle": 0.0},
+         "state": (R0 * med["rho0"], R0 * med["rho0"] * med["c0"], np.zeros_like(R0))}
+    _say(f"case: taylor bc {nx}x{ny} width {width:.2f} cells, adaptive")
+    g, st, sim = run_gpu(w, 120, "f64")
+    o, info = run_oracle(orc, w, 120)
+    assert st["status"] == 0 and info["status"] == 0
+    err = max_rel(g, o)
+    _say(f"  max rel err {err:.3e}")
+    assert err <= 1e-10
+    sim.fvna_destroy()
+
+
+@pytest.mark.parametrize("geometry", ["planar", "axisym"])
+def test_focused_source(orc, geometry):
+    """Focused source on x- (eq. hifuBC with a ramp), reflecting y- side."""
+    nx, ny = 160, 96
+    dx = 2e-5
+    src = {"freq": 1e6 * 4, "p_surface": 4e5, "focal_length": 120 * dx, "aperture": 60 * dx,
+           "ramp_cycles": 1.0}
+    w = pulse_workload(nx, ny, ("source", "extrap0", "reflect", "extrap0"), geometry=geometry,
+                       amplitude_pa=2e5, dx=dx, source=src, seed=3)
+    _say(f"case: focused source {geometry} {nx}x{ny} adaptive")
+    g, st, sim = run_gpu(w, 150, "f64")
+    o, info = run_oracle(orc, w, 150)
+    assert st["status"] == 0 and info["status"] == 0
+    err = max_rel(g, o, peak=np.max(np.abs(o[0])))
+    _say(f"  max rel err {err:.3e}")
+    assert err <= 1e-10
+    sim.fvna_destroy()
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_tile_shape_invariance_bitwise(precision):
+    w = pulse_workload(173, 141, ("extrap0", "reflect", "periodic", "periodic"), seed=5)
+    outs = []
+    for tile in (8, 24, 64, 256):
+        _say(f"case: tile invariance {precision} tile={tile}")
+        g, st, sim = run_gpu(w, 30, precision, tile_rows=tile)
+        outs.append(g)
+        sim.fvna_destroy()
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a, b)
+
+
+def test_repeat_and_split_runs_bitwise():
+    """Run-twice determinism and 20 + 20 steps == 40 steps, bitwise."""
+    w = pulse_workload(120, 90, ("extrap0",) * 4, seed=9)
+    _say("case: determinism / split runs")
+    a, _, s1 = run_gpu(w, 40, "f32")
+    b, _, s2 = run_gpu(w, 40, "f32")
+    _, _, s3 = run_gpu(w, 20, "f32")
+    c, st, _ = run_gpu(w, 20, "f32", sim=s3)
+    assert st["steps"] == 40
+    for x, y, z in zip(a, b, c):
+        assert np.array_equal(x, y) and np.array_equal(x, z)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_resume_from_exported_state_bitwise(precision):
+    """Export the state and clock, load them into a fresh context, continue:
+    bitwise equal to an uninterrupted run (unit conversions exact by choice of
+    power-of-two units)."""
+    from paper_1311_3004_amd import fvna
+    med = {"c0": 1024.0, "rho0": 1024.0, "beta": 3.5, "delta": 4e-6}
+    w = pulse_workload(100, 70, ("extrap0",) * 4, seed=11, medium=med, dx=2.0 ** -12)
+    _say(f"case: resume {precision}")
+    full, st_full, _ = run_gpu(w, 30, precision)
+    _, st_half, sim = run_gpu(w, 15, precision)
+    rp, mx, my = sim.fvna_get_state()
+    p = fvna.make_params(w["nx"], w["ny"], w["dx"], med, bc=w["bc"], precision=precision)
+    s2 = fvna.Sim(p)
+    s2.fvna_set_state(rp, mx, my)
+    s2.fvna_set_clock(st_half["t"], st_half["dt_next"])
+    s2.fvna_step(15)
+    out = [a / med["rho0"] for a in s2.fvna_get_state()]
+    out[1] /= med["c0"]; out[2] /= med["c0"]
+    for x, y in zip(full, out):
+        assert np.array_equal(x, y)
+
+
+def test_rejection_path_matches_oracle(orc):
+    """A first step three times too large is rejected and redone (CFL control)."""
+    w = pulse_workload(90, 60, ("extrap0",) * 4, seed=13)
+    dt_si = 3.0 * w["dx"] / w["medium"]["c0"]
+    _say("case: rejection path")
+    g, st, sim = run_gpu(w, 10, "f64", dt_si=dt_si)
+    o, info = run_oracle(orc, w, 10, dt_si=dt_si)
+    assert info["rejected"] == 1 and st["rejected"] == 1
+    assert max_rel(g, o) <= 1e-10
+
+
+def test_nonhyperbolic_state_is_reported(orc):
+    from paper_1311_3004_amd import fvna
+    w = pulse_workload(64, 64, ("extrap0",) * 4, seed=17)
+    rp, mx, my = w["state"]
+    rp = rp.copy()
+    rp[30:34, 30:34] = -0.6 * w["medium"]["rho0"]     # rho/rho0 = 0.4 at rest: outside S
+    w["state"] = (rp, mx, my)
+    _say("case: non-hyperbolic")
+    p = fvna.make_params(64, 64, w["dx"], w["medium"], bc=w["bc"], precision="f64", dt0=1e-8)
+    s = fvna.Sim(p)
+    s.fvna_set_state(*w["state"])
+    s.fvna_step(3)
+    assert s.fvna_sync(allow_device_errors=True) == fvna.E_NONHYPERBOLIC
+    st = s.fvna_get_stats(allow_device_errors=True)
+    assert st["status"] == fvna.E_NONHYPERBOLIC and st["steps"] == 0
+    out = s.fvna_get_state(allow_device_errors=True)
+    assert np.array_equal(out[0], rp)            # last accepted state kept
+    o, info = run_oracle(orc, w, 3, dt_si=1e-8)
+    assert info["status"] == orc.E_NONHYPERBOLIC
+
+
+def test_nan_is_reported():
+    from paper_1311_3004_amd import fvna
+    w = pulse_workload(64, 48, ("extrap0",) * 4, seed=19)
+    rp = w["state"][0].copy()
+    rp[10, 20] = np.nan
+    _say("case: nan")
+    p = fvna.make_params(64, 48, w["dx"], w["medium"], bc=w["bc"], precision="f32", dt0=1e-8)
+    s = fvna.Sim(p)
+    s.fvna_set_state(rp, w["state"][1], w["state"][2])
+    s.fvna_step(2)
+    assert s.fvna_sync(allow_device_errors=True) in (fvna.E_NONHYPERBOLIC, fvna.E_NONFINITE)
+
+
+def test_conservation_periodic_fp64():
+    w = pulse_workload(96, 80, ("periodic",) * 4, seed=21)
+    from paper_1311_3004_amd import fvna
+    _say("case: conservation")
+    s = fvna.sim_from_workload(w, precision="f64")
+    s0 = s.fvna_sums()
+    s.fvna_step(100)
+    s1 = s.fvna_sums()
+    rp, mx, my = w["state"]
+    scale = np.array([np.abs(rp).sum(), np.abs(mx).sum() + 1e-30, np.abs(my).sum() + 1e-30])
+    assert np.all(np.abs(s1 - s0) <= 1e-13 * scale)
+    ref = np.array([rp.sum(), mx.sum(), my.sum()])
+    assert np.all(np.abs(s0 - ref) <= 1e-13 * scale)
+
+
+def test_fp32_against_fp64_gaussian_512():
+    """FP32 path within 1e-5 of the FP64 path (max |dp|/p_peak), Gaussian workload."""
+    from paper_1311_3004_amd import inputs
+    w = inputs.c2_pulse_fp32(512, 512)
+    _say("case: fp32 vs fp64 512^2 300 steps")
+    a, sa, _ = run_gpu(w, 300, "f64")
+    b, sb, _ = run_gpu(w, 300, "f32")
+    err = float(np.max(np.abs(a[0] - b[0])) / np.max(np.abs(a[0])))
+    _say(f"  fp32 max |dp|/p_peak {err:.3e}")
+    assert err <= 1e-5
