@@ -333,3 +333,177 @@ def test_taylor_step_front_position(orc):
         fronts.append(k + 0.5 + row[k] / (row[k] - row[k + 1]))
     assert abs(np.mean(fronts) - (64.0 + info["t"])) < 0.5
     assert abs(info["nu_mean"] - 0.9) < 1e-3
+
+
+# -- Axisymmetric source terms: exact Bessel modes ------------------------------
+
+def _axisym_mode_run(orc, n, which, dt=0.45):
+    """Uniform in z (4 periodic columns), n cells in r, wall at r = n where
+    J1(k n) = 0 (reflecting side: zero normal momentum, even density).
+    which = 'shear': M = eps J0(k r) e^{-delta k^2 t}, R = N = 0 -- an exact solution
+    of the full axisymmetric system (tests delta (d2/dr2 + (1/r) d/dr) of u).
+    which = 'radial': R = eps J0(k r) A(t), N = eps J1(k r) B(t) -- exact for the
+    linearised system (tests -N/r in the mass equation and the cylindrical viscous
+    terms of v, including -v/r^2); A, B solve the same 2x2 system as a plane mode."""
+    from scipy.special import j0, j1, jn_zeros
+    eps = 1e-9 if which == "radial" else 1e-6
+    kL = jn_zeros(1, 2)[1] if which == "radial" else jn_zeros(1, 1)[0]
+    k = kL / n
+    delta = 0.02 * n / 32            # fixed physical diffusivity under refinement
+    T = 0.6 * n                      # fixed physical time
+    steps = int(round(T / dt))
+    dt = T / steps
+    r = np.arange(n) + 0.5
+    nz = 4
+    Z = np.zeros((n, nz))
+    if which == "shear":
+        M0 = np.repeat((eps * j0(k * r))[:, None], nz, axis=1)
+        R0, N0 = Z.copy(), Z.copy()
+    else:
+        R0 = np.repeat((eps * j0(k * r))[:, None], nz, axis=1)
+        M0, N0 = Z.copy(), Z.copy()
+    p = orc.make_params(nz, n, 3.5, delta, bc=("periodic", "periodic", "reflect", "reflect"),
+                        geometry="axisym", fixed_dt=True)
+    R1, M1, N1, info = orc.run(p, R0, M0, N0, steps, dt=dt)
+    assert info["status"] == 0
+    t = steps * dt
+    if which == "shear":
+        ex = eps * j0(k * r) * np.exp(-delta * k * k * t)
+        return np.mean(np.abs(M1[:, 0] - ex)) / np.mean(np.abs(ex))
+    g = delta * k * k / 2
+    Om = np.sqrt(k * k - g * g)
+    A = np.exp(-g * t) * (np.cos(Om * t) + g / Om * np.sin(Om * t))
+    # A' = -k B  =>  B = -A'/k
+    dA = np.exp(-g * t) * (-(Om + g * g / Om) * np.sin(Om * t))
+    B = -dA / k
+    exR = eps * j0(k * r) * A
+    exN = eps * j1(k * r) * B
+    eR = np.mean(np.abs(R1[:, 0] - exR)) / np.mean(np.abs(exR))
+    eN = np.mean(np.abs(N1[:, 0] - exN)) / np.mean(np.abs(exN))
+    assert np.all(M1 == 0.0)                 # no axial motion appears
+    return max(eR, eN)
+
+
+@pytest.mark.parametrize("which,dt", [("shear", 0.45), ("radial", 0.05)])
+def test_axisymmetric_bessel_modes_converge(orc, which, dt):
+    """Second order in space.  The radial mode is run at a small time step: its
+    hoop term -N/r is O(1) and the split step (sweeps, then the source by
+    forward Euler) carries an O(dt) splitting error, pinned separately below."""
+    ns = [32, 64, 128]
+    errs = [_axisym_mode_run(orc, n, which, dt) for n in ns]
+    rates = [np.log(errs[i] / errs[i + 1]) / np.log(2) for i in range(2)]
+    assert errs[-1] < 1e-2, errs
+    assert min(rates) > 1.6, (errs, rates)
+
+
+def test_axisymmetric_splitting_error_is_first_order_in_dt(orc):
+    """At a fixed mesh the radial-mode error falls linearly with dt until the
+    spatial error is reached: the signature of Godunov splitting of the source."""
+    e1 = _axisym_mode_run(orc, 128, "radial", 0.45)
+    e2 = _axisym_mode_run(orc, 128, "radial", 0.2)
+    e3 = _axisym_mode_run(orc, 128, "radial", 0.05)
+    assert e1 > e2 > e3
+    assert 1.6 < e1 / e2 < 2.6
+
+
+def test_axisymmetric_terms_are_needed(orc):
+    """The same radial mode run as planar geometry misses the cylindrical terms
+    and does not converge to the Bessel solution: the pin has teeth."""
+    from scipy.special import j0, jn_zeros
+    n, eps = 64, 1e-9
+    k = jn_zeros(1, 2)[1] / n
+    r = np.arange(n) + 0.5
+    R0 = np.repeat((eps * j0(k * r))[:, None], 4, axis=1)
+    Z = np.zeros_like(R0)
+    p = orc.make_params(4, n, 3.5, 0.04, bc=("periodic", "periodic", "reflect", "reflect"),
+                        geometry="planar", fixed_dt=True)
+    R1, M1, N1, info = orc.run(p, R0, Z, Z, 85, dt=0.45)
+    t = 85 * 0.45
+    g = 0.04 * k * k / 2
+    Om = np.sqrt(k * k - g * g)
+    exR = eps * j0(k * r) * np.exp(-g * t) * (np.cos(Om * t) + g / Om * np.sin(Om * t))
+    assert np.mean(np.abs(R1[:, 0] - exR)) / np.mean(np.abs(exR)) > 0.05
+
+
+# -- Exact viscous travelling shock of the model system ------------------------
+
+def travelling_profile(beta, delta, a, xi):
+    """Exact travelling wave of the 1-D model (no tangential motion), right
+    state R = -a at rest, left state R = +a.  Rankine-Hugoniot gives the speed
+    V and the left momentum; the profile solves
+      delta u' = -V M + u^2 + phi(R) - phi(R_R),  M = V (R - R_R),  u = M/(1+R),
+    i.e. R' = H(R) (1+R)^2 / (delta V (1 + R_R)); integrated with RK4 from
+    R(0) = 0 in both directions.  Returns V, R(xi), M(xi)."""
+    RR, RL = -a, a
+    phi = lambda R: R + (beta - 1) * R * R
+    dR = RL - RR
+    V = np.sqrt((phi(RL) - phi(RR)) / (dR * (1 - dR / (1 + RL) ** 2)))
+
+    def H(R):
+        M = V * (R - RR)
+        u = M / (1 + R)
+        return -V * M + u * u + phi(R) - phi(RR)
+
+    def f(R):
+        return H(R) * (1 + R) ** 2 / (delta * V * (1 + RR))
+
+    xi = np.asarray(xi, dtype=float)
+    out = np.empty_like(xi)
+    h = 1e-3 * delta / (beta * a)
+    for sign in (1, -1):
+        sel = np.sign(xi) == sign if sign > 0 else xi < 0
+        if sign > 0:
+            sel = xi >= 0
+        pts = np.sort(np.abs(xi[sel]))
+        R, x, vals = 0.0, 0.0, {}
+        for target in pts:
+            while x < target - 1e-15:
+                hh = min(h, target - x)
+                s = sign * hh
+                k1 = f(R); k2 = f(R + 0.5 * s * k1); k3 = f(R + 0.5 * s * k2); k4 = f(R + s * k3)
+                R += s * (k1 + 2 * k2 + 2 * k3 + k4) / 6
+                x += hh
+            vals[target] = R
+        out[sel] = [vals[abs(v)] for v in xi[sel]]
+    return V, out, V * (out - RR)
+
+
+@pytest.mark.slow
+def test_exact_viscous_shock_profile_second_order(orc):
+    beta, a = 4.0, 3e-3
+    errs = []
+    etas = [4, 8, 16]
+    for eta in etas:
+        delta = beta * a * eta            # profile width delta/(beta a) = eta cells
+        nx, ny = 40 * eta, 4
+        x0 = 12.0 * eta
+        x = np.arange(nx) + 0.5
+        V, R0, M0 = travelling_profile(beta, delta, a, x - x0)
+        R0 = np.broadcast_to(R0, (ny, nx)).copy()
+        M0 = np.broadcast_to(M0, (ny, nx)).copy()
+        p = orc.make_params(nx, ny, beta, delta, bc=("extrap0", "extrap0", "periodic", "periodic"),
+                            fixed_dt=True)
+        dt = 0.5
+        steps = int(round(12 * eta / dt))
+        R1, M1, N1, info = orc.run(p, R0, M0, np.zeros_like(R0), steps, dt=dt)
+        assert info["status"] == 0
+        _, Rex, _ = travelling_profile(beta, delta, a, x - x0 - V * steps * dt)
+        errs.append(np.sum(np.abs(R1[0] - Rex)) / np.sum(np.abs(Rex)))
+    rates = [np.log(errs[i] / errs[i + 1]) / np.log(2) for i in range(2)]
+    assert errs[-1] < 5e-3, errs
+    assert min(rates) > 1.6, (errs, rates)
+
+
+def test_travelling_speed_matches_rankine_hugoniot():
+    """The speed formula, checked against the survey's worked value and against
+    the jump conditions written out independently."""
+    beta, a = 4.0, 3e-3
+    V, _, _ = travelling_profile(beta, 0.04, a, np.array([0.0]))
+    assert abs(V - 1.00300) < 5e-6
+    RL, RR = a, -a
+    ML = V * (RL - RR)
+    uL = ML / (1 + RL)
+    flux_mom = lambda M, u, R: u * u + R + (beta - 1) * R * R
+    # mass: V [R] = [M];  momentum: V [M] = [u^2 + phi]
+    assert abs(V * (RL - RR) - ML) < 1e-15
+    assert abs(V * ML - (flux_mom(ML, uL, RL) - flux_mom(0.0, 0.0, RR))) < 1e-15
