@@ -23,6 +23,8 @@
  *   ghosts(x) of Q^n -> x1 sweep -> ghosts(y) of Q* -> x2 sweep (components
  *   2 and 3 swapped) -> one ghost layer of Q** -> source -> Q^{n+1};
  *   then the CFL number of the step decides acceptance (Sec. 4 opening).
+ *   In axisymmetric geometry the geometric terms enter as two half steps
+ *   around the x2 sweep (geometric_half_step).
  *
  * Readings of points the paper leaves open are stated where they are used.
  * Parity status of each function is stated in its comment; the pins that fix
@@ -387,11 +389,10 @@ static void fill_ghosts_y(const orc_params *p, double t, field_t *g, int layers)
  * the Laplacian of the velocity u = q^2/q^1, as the physical right-hand side
  * rho0 delta lap(u) of eq. OurSystem requires.
  * Axisymmetric (x1 = z, x2 = r, r_j = j + 1/2; not in the paper, derived from
- * eq. OurSystem in cylindrical coordinates without swirl): the divergence of
- * rho0 u(x)u + pI adds -N/r to the mass equation and -u v/r, -v^2/r to the
- * momenta; the vector Laplacian adds (1/r) d/dr of each velocity component
- * and -v/r^2 to the radial one.  Parity of this branch rests on the
- * spherical-wave pin, not on the paper. */
+ * eq. OurSystem in cylindrical coordinates without swirl): the vector
+ * Laplacian adds (1/r) d/dr of each velocity component and -v/r^2 to the
+ * radial one.  The geometric (hoop) terms of the divergence are not part of
+ * this step: see geometric_half_step. */
 static void source_step(const orc_params *p, double dt, field_t *in, field_t *out)
 {
     int nx = in->nx, ny = in->ny;
@@ -415,9 +416,8 @@ static void source_step(const orc_params *p, double dt, field_t *in, field_t *ou
                 double r = j + 0.5;
                 double dur = (u[yp] - u[ym]) / 2.0;
                 double dvr = (v[yp] - v[ym]) / 2.0;
-                sR = -in->N[c] / r;
-                sM = -u[c] * v[c] / r + p->delta * (lapu + dur / r);
-                sN = -v[c] * v[c] / r + p->delta * (lapv + dvr / r - v[c] / (r * r));
+                sM = p->delta * (lapu + dur / r);
+                sN = p->delta * (lapv + dvr / r - v[c] / (r * r));
             } else {
                 sM = p->delta * lapu;
                 sN = p->delta * lapv;
@@ -428,6 +428,33 @@ static void source_step(const orc_params *p, double dt, field_t *in, field_t *ou
         }
     free(u);
     free(v);
+}
+
+/* Axisymmetric geometric terms (not in the paper; derived from eq.
+ * OurSystem in cylindrical coordinates without swirl): the divergence of
+ * rho u and of rho0 u(x)u + pI adds -N/r to the mass equation, -u v/r to the
+ * axial and -v^2/r to the radial momentum (the pressure parts cancel).  They
+ * are applied by forward Euler over half a time step, in place, on the
+ * interior cells, once before and once after the x2 sweep (the sweep that
+ * carries the radial flux): applied only after both sweeps the split step is
+ * unstable near the axis above CFL ~0.8, applied symmetrically around the x2
+ * sweep it is stable up to CFL 1 and second order in time. */
+static void geometric_half_step(const orc_params *p, double h, field_t *f)
+{
+    for (int j = 0; j < f->ny; j++) {
+        double r = j + 0.5;
+        for (int i = 0; i < f->nx; i++) {
+            size_t c = idx(f, i, j);
+            double q1 = 1.0 + f->R[c];
+            double u = f->M[c] / q1, v = f->N[c] / q1;
+            double sR = -f->N[c] / r;
+            double sM = -u * v / r;
+            double sN = -v * v / r;
+            f->R[c] = f->R[c] + h * sR;
+            f->M[c] = f->M[c] + h * sM;
+            f->N[c] = f->N[c] + h * sN;
+        }
+    }
 }
 
 /* ------------------------------------------------------------------------- */
@@ -476,6 +503,7 @@ static int attempt(const orc_params *p, work_t *w, double t, double dt, double *
             w->b.R[d] = w->or_[i]; w->b.M[d] = w->on[i]; w->b.N[d] = w->ot[i];
         }
     }
+    if (p->geometry == GEOM_AXISYM) geometric_half_step(p, 0.5 * dt, &w->b);
     /* x2 sweep on Q*: same scheme with components 2 and 3 swapped */
     fill_ghosts_y(p, t, &w->b, 2);
     for (int i = 0; i < nx; i++) {
@@ -490,6 +518,7 @@ static int attempt(const orc_params *p, work_t *w, double t, double dt, double *
             w->c.R[d] = w->or_[j]; w->c.N[d] = w->on[j]; w->c.M[d] = w->ot[j];
         }
     }
+    if (p->geometry == GEOM_AXISYM) geometric_half_step(p, 0.5 * dt, &w->c);
     /* source on Q** with one ghost layer */
     fill_ghosts_x(p, t, &w->c, 1);
     fill_ghosts_y(p, t, &w->c, 1);
