@@ -53,7 +53,7 @@ def timed_run(sim, steps, warmup):
     accepted = st1["steps"] - st0["steps"]
     return {"wall_s": t1 - t0, "event_s": e0.elapsed_time(e1) / 1e3, "accepted": accepted,
             "rejected": st1["rejected"] - st0["rejected"], "nu_mean": st1["nu_mean"],
-            "nu_std": st1["nu_std"]}
+            "nu_std": st1["nu_std"], "t": st1["t"]}
 
 
 def kernel_roofline(sim, precision, cells, reps=20):
@@ -138,7 +138,8 @@ def main():
                          "ms_per_step": round(r64["event_s"] * 1e3 / args.steps, 4),
                          "kernel_ms": round(ms64, 4), "hbm_frac": round(gbs64 / HBM_PEAK_GBS, 4)}
         extra["fp32_error_vs_fp64"] = {"max_abs_dp_over_p_peak": err, "rel_l2": l2,
-                                       "steps": args.warmup + args.steps}
+                                       "steps": args.warmup + args.steps,
+                                       "time_rel_diff": abs(r32["t"] - r64["t"]) / r64["t"]}
         extra["fp32_over_fp64"] = round(v32 / v64, 3)
 
     # ---- batched form: 64 uneven simulations vs 64 sequential runs ----

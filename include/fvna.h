@@ -173,6 +173,13 @@ fvna_status fvna_sync(fvna_ctx* c);
 /* Synchronise and copy the current state out (same units and layout as set_state). */
 fvna_status fvna_get_state(fvna_ctx* c, double* rho_p, double* mom_x, double* mom_y);
 
+/* Synchronise and copy the window [i0, i0 + ni) x [j0, j0 + nj) of the current
+ * state out, in the units of fvna_get_state, as arrays [nj][ni].  For probes
+ * (e.g. a row of cells sampled every step) and sub-region comparisons without
+ * exporting the whole grid.  The window must lie inside the grid. */
+fvna_status fvna_get_window(fvna_ctx* c, int32_t i0, int32_t j0, int32_t ni, int32_t nj,
+                            double* rho_p, double* mom_x, double* mom_y);
+
 /* Synchronise and return the clock and CFL statistics. */
 fvna_status fvna_get_stats(fvna_ctx* c, fvna_stats* s);
 

@@ -48,7 +48,7 @@ constexpr int OUTW = WAVE - 2 * HALO;   // 58 output columns per wavefront
 constexpr int WAVES_PER_BLOCK = 4;
 
 enum { BC_PERIODIC = 0, BC_EXTRAP0 = 1, BC_REFLECT = 2, BC_TAYLOR = 3, BC_SOURCE = 4 };
-enum { FLAG_NONHYP = 1u };
+enum { FLAG_NONHYP = 1u, FLAG_NONFINITE = 2u };
 enum { ST_OK = 0, ST_NONHYP = 4, ST_NONFINITE = 5, ST_RETRIES = 6 };
 
 // Device-resident clock and control word of one simulation.  Written only by
@@ -126,6 +126,10 @@ __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double sqrt_(double x) { return __builtin_sqrt(x); }
 __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
+// c = sqrt(D) and ic = 1/c: FP64 keeps the correctly rounded square root and
+// division; FP32 uses one reciprocal square root (1 ulp) and a product.
+__device__ __forceinline__ void sqrt_pair(double D, double& c, double& ic) { c = __builtin_sqrt(D); ic = 1.0 / c; }
+__device__ __forceinline__ void sqrt_pair(float D, float& c, float& ic) { ic = __builtin_amdgcn_rsqf(D); c = D * ic; }
 __device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double abs_(double x) { return __builtin_fabs(x); }
@@ -158,20 +162,34 @@ template <typename T> struct Wave { T s1, s2, s3, a1, a2, a3, r1, r2; };
 // w = zn/rho and s - w = +-c; strengths from sum_p alpha^p r^p = Q_R - Q_L.
 // L and R hold (density perturbation, normal momentum, tangential momentum)
 // and the two velocities.  Returns false if the discriminant is not positive.
+//
+// cfl receives this interface's max_p |s^p| = c + |w| in a form the CFL
+// reduction can carry exactly: FP64 returns it as is; FP32 returns its excess
+// over 1, (c - 1) + |w| with c - 1 = (D - 1)/(1 + c), which keeps ~1e-7
+// relative precision on the excess (so ~1e-10 on the speed itself).  nonfinite
+// is set when the discriminant is +Inf (the FP32 square root pair would turn
+// it into NaN).
 template <typename T>
 __device__ __forceinline__ bool roe(T RL, T nL, T tL, T vnL, T vtL,
-                                    T RR, T nR, T tR, T vnR, T vtR, T beta, Wave<T>& w)
+                                    T RR, T nR, T tR, T vnR, T vtR, T beta, Wave<T>& w,
+                                    T& cfl, bool& nonfinite)
 {
     const T Rb = T(0.5) * (RL + RR);              // Zbar^1 - 1
     const T irb = rcp(T(1) + Rb);
     const T zn = T(0.5) * (vnL + vnR);
     const T zt = T(0.5) * (vtL + vtR);
     const T wv = zn * irb;
-    const T Phi = fma_(T(2) * (beta - T(1)), Rb, T(1));
-    const T D = fma_(wv, wv - T(2) * zn, Phi);    // w^2 - 2 zn^2/Zbar^1 + Phi
+    const T D1 = fma_(wv, wv - T(2) * zn, T(2) * (beta - T(1)) * Rb);   // D - 1
+    const T D = T(1) + D1;                        // w^2 - 2 zn^2/Zbar^1 + Phi
     const bool ok = D > T(0);
-    const T c = sqrt_(D);
-    const T ic = rcp(c);
+    T c, ic;
+    sqrt_pair(D, c, ic);
+    if constexpr (sizeof(T) == 8) {
+        cfl = c + abs_(wv);
+    } else {
+        cfl = fma_(D1, rcp(T(1) + c), abs_(wv));
+        nonfinite = nonfinite | !(D < __builtin_inff());
+    }
     w.s1 = wv + c;
     w.s2 = wv - c;
     w.s3 = wv;
@@ -185,6 +203,15 @@ __device__ __forceinline__ bool roe(T RL, T nL, T tL, T vnL, T vtL,
     return ok;
 }
 
+// Value the CFL reduction starts from (no interface counted yet) and the
+// largest wave speed a reduced value stands for.
+template <typename T> __device__ __forceinline__ T cfl_floor() { return sizeof(T) == 8 ? T(0) : T(-1); }
+template <typename T> __device__ __forceinline__ double cfl_speed(T m)
+{
+    if constexpr (sizeof(T) == 8) return m;
+    else return 1.0 + (double)m;
+}
+
 // MC limiter (Sec. 3.1): phi = max(0, min((1 + theta)/2, 2, 2 theta)).
 template <typename T>
 __device__ __forceinline__ T mc(T th)
@@ -192,46 +219,76 @@ __device__ __forceinline__ T mc(T th)
     return max_(T(0), min_(min_(T(0.5) * (T(1) + th), T(2)), T(2) * th));
 }
 
-// theta = (W_up . W) / (W . W) with W = alpha (1, s, r) (theta = 0 when W = 0).
+// Products W^p_a . W^p_b of the waves of two neighbouring interfaces, per
+// family, with W^p = alpha^p (1, s^p, r^p) for p = 1, 2 and W^3 = (0, 0, alpha^3).
 template <typename T>
-__device__ __forceinline__ T theta_ac(T a, T s, T r, T au, T su, T ru)
+__device__ __forceinline__ void wave_dots(const Wave<T>& a, const Wave<T>& b, T d[3])
 {
-    const T num = au * a * fma_(ru, r, fma_(su, s, T(1)));
-    const T den = a * a * fma_(r, r, fma_(s, s, T(1)));
-    return den != T(0) ? num * rcp(den) : T(0);
+    d[0] = (a.a1 * b.a1) * fma_(a.r1, b.r1, fma_(a.s1, b.s1, T(1)));
+    d[1] = (a.a2 * b.a2) * fma_(a.r2, b.r2, fma_(a.s2, b.s2, T(1)));
+    d[2] = a.a3 * b.a3;
 }
 
-// From the interface's waves and its upwind neighbours' waves (per family),
-// form Gm = A^- dQ + F~ (the part applied to the cell on the low side) and
-// Gp = A^+ dQ - F~ (the part applied to the cell on the high side); eqs.
-// fluc:m, fluc:p, limiter, fv-hr.  Components in split-local order.
+// theta = (W_up . W) / (W . W) (Sec. 3.1).  The paper's method needs theta
+// only through phi(theta) alpha; when W = 0 (alpha = 0) the quotient is 0/0 or
+// x/0, phi is then 0 or 2 (min/max return the non-NaN operand), and the
+// product with alpha = 0 is 0 -- the value the guard theta := 0 gives.  So no
+// guard is evaluated.
 template <typename T>
-__device__ __forceinline__ void hr_split(const Wave<T>& w,
-                                         T a1u, T s1u, T r1u, T a2u, T s2u, T r2u, T a3u,
-                                         T dt, T Gm[3], T Gp[3])
+__device__ __forceinline__ T theta_of(T dup, T a, T s, T r)
 {
-    const T ph1 = mc(theta_ac(w.a1, w.s1, w.r1, a1u, s1u, r1u));
-    const T ph2 = mc(theta_ac(w.a2, w.s2, w.r2, a2u, s2u, r2u));
-    const T th3 = (w.a3 != T(0)) ? (a3u * w.a3) * rcp(w.a3 * w.a3) : T(0);
-    const T ph3 = mc(th3);
+    const T den = (a * a) * fma_(r, r, fma_(s, s, T(1)));
+    return dup * rcp(den);
+}
+
+// From the waves of one interface and the products of its waves with those of
+// the interface below (dlo) and above (dhi), form
+//   Gm = A^- dQ + F~   (applied to the cell on the low side) and
+//   Gp = A^+ dQ - F~   (applied to the cell on the high side);
+// eqs. fluc:m, fluc:p, limiter, fv-hr.  The upwind interface of family p is
+// the one below when s^p >= 0 and the one above when s^p < 0.  Components in
+// split-local order (density, normal, tangential momentum).
+template <typename T>
+__device__ __forceinline__ void hr_split(const Wave<T>& w, const T dlo[3], const T dhi[3], T dt,
+                                         T Gm[3], T Gp[3])
+{
+    const T ph1 = mc(theta_of(w.s1 < T(0) ? dhi[0] : dlo[0], w.a1, w.s1, w.r1));
+    const T ph2 = mc(theta_of(w.s2 < T(0) ? dhi[1] : dlo[1], w.a2, w.s2, w.r2));
+    const T ph3 = mc((w.s3 < T(0) ? dhi[2] : dlo[2]) * rcp(w.a3 * w.a3));
     const T as1 = abs_(w.s1), as2 = abs_(w.s2), as3 = abs_(w.s3);
     // correction strengths c_p = 1/2 |s| (1 - dt |s|) phi alpha
-    const T c1 = T(0.5) * as1 * fma_(-dt, as1, T(1)) * ph1 * w.a1;
-    const T c2 = T(0.5) * as2 * fma_(-dt, as2, T(1)) * ph2 * w.a2;
-    const T c3 = T(0.5) * as3 * fma_(-dt, as3, T(1)) * ph3 * w.a3;
-    // e_p = min(s,0) alpha + c_p ; g_p = max(s,0) alpha - c_p
+    const T hdt = T(0.5) * dt;
+    const T c1 = (fma_(-hdt, as1, T(0.5)) * as1) * (ph1 * w.a1);
+    const T c2 = (fma_(-hdt, as2, T(0.5)) * as2) * (ph2 * w.a2);
+    const T c3 = (fma_(-hdt, as3, T(0.5)) * as3) * (ph3 * w.a3);
+    // e_p = min(s,0) alpha + c_p ; g_p = max(s,0) alpha - c_p = s alpha - e_p
     const T e1 = fma_(min_(w.s1, T(0)), w.a1, c1);
     const T e2 = fma_(min_(w.s2, T(0)), w.a2, c2);
     const T e3 = fma_(min_(w.s3, T(0)), w.a3, c3);
-    const T g1 = fma_(max_(w.s1, T(0)), w.a1, -c1);
-    const T g2 = fma_(max_(w.s2, T(0)), w.a2, -c2);
-    const T g3 = fma_(max_(w.s3, T(0)), w.a3, -c3);
+    const T g1 = fma_(w.s1, w.a1, -e1);
+    const T g2 = fma_(w.s2, w.a2, -e2);
+    const T g3 = fma_(w.s3, w.a3, -e3);
     Gm[0] = e1 + e2;
     Gm[1] = fma_(e1, w.s1, e2 * w.s2);
     Gm[2] = fma_(e1, w.r1, fma_(e2, w.r2, e3));
     Gp[0] = g1 + g2;
     Gp[1] = fma_(g1, w.s1, g2 * w.s2);
     Gp[2] = fma_(g1, w.r1, fma_(g2, w.r2, g3));
+}
+
+// Axisymmetric geometric terms of the divergence (cylindrical coordinates,
+// no swirl): d/dt (R, M, N) = -(N, u v, v^2)/r, applied by forward Euler over
+// h = dt/2 on one cell in place; hr = h / r.  Used once on each x1-swept row
+// before the x2 sweep and once on each x2-swept row after it (the symmetric
+// placement keeps the split step stable near the axis up to CFL 1).
+template <typename T>
+__device__ __forceinline__ void geometric_half_step(Cell<T>& q, T hr)
+{
+    const T ir = rcp(T(1) + q.R);
+    const T u = q.M * ir, v = q.N * ir;
+    q.R = fma_(-hr, q.N, q.R);
+    q.M = fma_(-hr, u * v, q.M);
+    q.N = fma_(-hr, v * v, q.N);
 }
 
 // ---------------------------------------------------------------------------
@@ -278,18 +335,35 @@ __device__ __forceinline__ void source_at(const SimDesc& d, double r, double t, 
 // The fused step of one wavefront tile.
 // ---------------------------------------------------------------------------
 
-// x2-sweep pipeline state of one lane (its column).
-template <typename T> struct Pipe {
-    Cell<T> p1; T pu1, pv1;       // x1-swept row v-1 and its velocities
-    Cell<T> p2;                   // x1-swept row v-2
-    Wave<T> wB, wC;               // x2 interfaces v-3/2 and v-5/2
-    T gpC[3];                     // Gp of interface v-5/2 (applied to row v-2)
-    Cell<T> qc; T uc, vc;         // x2-swept row v-3 (its source comes next)
-    T ub, vb;                     // velocities of x2-swept row v-4
-    Cell<T> stash;                // x1-swept row ny-2 (reflecting top ghost)
+
+// State one lane carries from one x2 row to the next.  Every entry is
+// consumed by the very next row, so two copies alternated by a two-row
+// unrolled loop need no register moves.
+template <typename T> struct Carry {
+    Cell<T> q; T u, v;      // last x1-swept row Q*_v pushed, and its velocities
+    Wave<T> w;              // x2 interface v - 1/2
+    T dlo[3];               // W_{v-3/2} . W_{v-1/2} per family
+    Cell<T> part;           // Q*_{v-1} - dt Gp_{v-3/2}: row v-1 awaiting its upper flux
+    Cell<T> qs; T us, vs;   // x2-swept row v-2 awaiting its source, and its velocities
+    T ub, vb;               // velocities of x2-swept row v-3
 };
 
-template <typename S, typename T, int AXI>
+template <typename T>
+__device__ __forceinline__ void carry_zero(Carry<T>& c)
+{
+    const T z = T(0);
+    c.q = {z, z, z}; c.u = z; c.v = z;
+    c.w = {z, z, z, z, z, z, z, z};
+    c.dlo[0] = c.dlo[1] = c.dlo[2] = z;
+    c.part = {z, z, z};
+    c.qs = {z, z, z}; c.us = z; c.vs = z;
+    c.ub = z; c.vb = z;
+}
+
+// One wavefront tile of the fused step.  EDGE: the strip touches a
+// non-periodic x side (ghost columns and x overrides needed); interior strips
+// compile without any of that logic.
+template <typename S, typename T, int AXI, bool EDGE>
 __device__ __forceinline__ void march(const SimDesc& d, int strip, int seg, bool count)
 {
     using C = Codec<S, T>;
@@ -315,6 +389,7 @@ __device__ __forceinline__ void march(const SimDesc& d, int strip, int seg, bool
     const bool pery = d.bc[2] == BC_PERIODIC;
     const T beta = (T)d.beta;
     const T delta = (T)d.delta;
+    const T hdt = T(0.5) * dt;
     const float sc0 = d.scale[0], sc1 = d.scale[1], sc2 = d.scale[2];
     const float is0 = d.inv_scale[0], is1 = d.inv_scale[1], is2 = d.inv_scale[2];
 
@@ -325,83 +400,93 @@ __device__ __forceinline__ void march(const SimDesc& d, int strip, int seg, bool
     int xkind = 0;          // 0: load; 1: Taylor; 2: focused source (else extrapolate)
     if (perx) {
         scol = ((col % nx) + nx) % nx;
-    } else if (col < 0) {
-        const int g = -col;
-        switch (d.bc[0]) {
-        case BC_REFLECT: scol = g - 1; msign = T(-1); break;
-        case BC_TAYLOR: xkind = 1; scol = 0; break;
-        case BC_SOURCE: xkind = 2; scol = 0; break;
-        default: scol = 0; break;
+    } else if (EDGE) {
+        if (col < 0) {
+            const int g = -col;
+            switch (d.bc[0]) {
+            case BC_REFLECT: scol = g - 1; msign = T(-1); break;
+            case BC_TAYLOR: xkind = 1; scol = 0; break;
+            case BC_SOURCE: xkind = 2; scol = 0; break;
+            default: scol = 0; break;
+            }
+        } else if (col >= nx) {
+            const int g = col - nx + 1;
+            switch (d.bc[1]) {
+            case BC_REFLECT: scol = nx - g; msign = T(-1); break;
+            case BC_TAYLOR: xkind = 1; scol = nx - 1; break;
+            default: scol = nx - 1; break;
+            }
         }
-    } else if (col >= nx) {
-        const int g = col - nx + 1;
-        switch (d.bc[1]) {
-        case BC_REFLECT: scol = nx - g; msign = T(-1); break;
-        case BC_TAYLOR: xkind = 1; scol = nx - 1; break;
-        default: scol = nx - 1; break;
-        }
+        scol = min(max(scol, 0), nx - 1);
     }
-    scol = min(max(scol, 0), nx - 1);
     const bool real_col = perx || incol;
     const bool cnt_x = count && lane >= 1 && (perx || (col >= 0 && col <= nx));
     const bool cnt_y = count && lane >= 2 && lane <= WAVE - 3 && real_col;
     const bool out_lane = lane >= HALO && lane < WAVE - HALO && col < nx;
     const int lm1 = lane - 1, lp1 = lane + 1;
+    const bool ghost_lo = EDGE && !perx && col == 0;        // left neighbour of this output cell is a ghost
+    const bool ghost_hi = EDGE && !perx && col == nx - 1;   // right neighbour is a ghost
 
-    T smax = T(0);
-    bool bad = false;
+    T smax = cfl_floor<T>();
+    bool bad = false, nonfin = false;
 
-    // ---- one x1-swept row (real row index vr in [0, ny)) ----
-    auto xsweep = [&](int vr) -> Cell<T> {
+    // ---- raw loads of one row of Q^n (real row index) ----
+    auto load_row = [&](int vr, S& a, S& b, S& c) {
         const size_t o = (size_t)vr * pitch + (size_t)scol;
+        a = inR[o];
+        b = inM[o];
+        c = inN[o];
+    };
+
+    // ---- x1 sweep of one row (lane-parallel) ----
+    auto xsweep = [&](int vr, S ra, S rb, S rc) -> Cell<T> {
         Cell<T> q;
-        q.R = C::ld(inR[o], sc0);
-        q.M = msign * C::ld(inM[o], sc1);
-        q.N = C::ld(inN[o], sc2);
-        if (xkind == 1) {
-            double R, M, N;
-            taylor_at(d, col + 0.5, vr + 0.5, tn, R, M, N);
-            q.R = (T)R; q.M = (T)M; q.N = (T)N;
-        } else if (xkind == 2) {
-            const double r = vr + 0.5;
-            if (r <= d.sr_ap) source_at<T>(d, r, tn, q.R, q.M, q.N);
+        q.R = C::ld(ra, sc0);
+        q.M = C::ld(rb, sc1);
+        q.N = C::ld(rc, sc2);
+        if (EDGE) {
+            q.M *= msign;
+            if (xkind == 1) {
+                double R, M, N;
+                taylor_at(d, col + 0.5, vr + 0.5, tn, R, M, N);
+                q.R = (T)R; q.M = (T)M; q.N = (T)N;
+            } else if (xkind == 2) {
+                const double r = vr + 0.5;
+                if (r <= d.sr_ap) source_at<T>(d, r, tn, q.R, q.M, q.N);
+            }
         }
         const T irho = rcp(T(1) + q.R);
         const T u = q.M * irho, v = q.N * irho;
         const T RL = perm(q.R, lm1), ML = perm(q.M, lm1), NL = perm(q.N, lm1);
         const T uL = perm(u, lm1), vL = perm(v, lm1);
         Wave<T> w;
-        const bool ok = roe(RL, ML, NL, uL, vL, q.R, q.M, q.N, u, v, beta, w);
+        T cfl;
+        bool nf = false;
+        const bool ok = roe(RL, ML, NL, uL, vL, q.R, q.M, q.N, u, v, beta, w, cfl, nf);
         if (cnt_x) {
             bad |= !ok;
-            smax = max_(smax, max_(abs_(w.s1), max_(abs_(w.s2), abs_(w.s3))));
+            nonfin |= nf;
+            smax = max_(smax, cfl);
         }
-        const int u1 = w.s1 < T(0) ? lp1 : lm1;
-        const int u2 = w.s2 < T(0) ? lp1 : lm1;
-        const int u3 = w.s3 < T(0) ? lp1 : lm1;
-        const T a1u = perm(w.a1, u1), s1u = perm(w.s1, u1), r1u = perm(w.r1, u1);
-        const T a2u = perm(w.a2, u2), s2u = perm(w.s2, u2), r2u = perm(w.r2, u2);
-        const T a3u = perm(w.a3, u3);
+        // waves of the interface to the right -> products with it; the lane
+        // to the left supplies the products with the interface below
+        Wave<T> wr;
+        wr.a1 = perm(w.a1, lp1); wr.s1 = perm(w.s1, lp1); wr.r1 = perm(w.r1, lp1);
+        wr.a2 = perm(w.a2, lp1); wr.s2 = perm(w.s2, lp1); wr.r2 = perm(w.r2, lp1);
+        wr.a3 = perm(w.a3, lp1);
+        T dhi[3], dlo[3];
+        wave_dots(w, wr, dhi);
+        dlo[0] = perm(dhi[0], lm1); dlo[1] = perm(dhi[1], lm1); dlo[2] = perm(dhi[2], lm1);
         T Gm[3], Gp[3];
-        hr_split(w, a1u, s1u, r1u, a2u, s2u, r2u, a3u, dt, Gm, Gp);
+        hr_split(w, dlo, dhi, dt, Gm, Gp);
         const T g0 = perm(Gm[0], lp1), g1 = perm(Gm[1], lp1), g2 = perm(Gm[2], lp1);
         Cell<T> o2;
         o2.R = fma_(-dt, g0 + Gp[0], q.R);
         o2.M = fma_(-dt, g1 + Gp[1], q.M);
         o2.N = fma_(-dt, g2 + Gp[2], q.N);
+        if constexpr (AXI) geometric_half_step(o2, hdt * rcp(T(vr) + T(0.5)));
         return o2;
     };
-
-    // ---- x2 pipeline ----
-    Pipe<T> P;
-    {
-        const T z = T(0);
-        P.p1 = {z, z, z}; P.pu1 = z; P.pv1 = z; P.p2 = {z, z, z};
-        P.wB = {z, z, z, z, z, z, z, z}; P.wC = P.wB;
-        P.gpC[0] = P.gpC[1] = P.gpC[2] = z;
-        P.qc = {z, z, z}; P.uc = z; P.vc = z; P.ub = z; P.vb = z; P.stash = {z, z, z};
-    }
-    const int vfirst = r0 - HALO;
 
     // analytic (Taylor) velocities of a ghost cell
     auto taylor_uv = [&](double x, double y, T& uu, T& vv) {
@@ -411,83 +496,90 @@ __device__ __forceinline__ void march(const SimDesc& d, int strip, int seg, bool
         vv = (T)(N / (1.0 + R));
     };
 
-    auto push = [&](Cell<T> q, int v) {
+    const int vfirst = r0 - HALO;
+
+    // ---- push x1-swept row v through the x2 sweep and the source ----
+    auto push = [&](const Cell<T>& q, int v, const Carry<T>& in, Carry<T>& out) {
         const T irho = rcp(T(1) + q.R);
         const T u = q.M * irho, vv = q.N * irho;
-        // stage A: x2 interface v-1/2 between rows v-1 (low) and v (high); normal = N
+        // x2 interface v-1/2 between rows v-1 (low) and v (high); normal = N
         Wave<T> wA;
-        const bool ok = roe(P.p1.R, P.p1.N, P.p1.M, P.pv1, P.pu1, q.R, q.N, q.M, vv, u, beta, wA);
+        T cfl;
+        bool nf = false;
+        const bool ok = roe(in.q.R, in.q.N, in.q.M, in.v, in.u, q.R, q.N, q.M, vv, u, beta, wA, cfl, nf);
         if (cnt_y && v > vfirst && (pery || (v >= 0 && v <= ny))) {
             bad |= !ok;
-            smax = max_(smax, max_(abs_(wA.s1), max_(abs_(wA.s2), abs_(wA.s3))));
+            nonfin |= nf;
+            smax = max_(smax, cfl);
         }
-        // stage B: limited correction at v-3/2 (upwind: v-5/2 if s >= 0, v-1/2 if s < 0)
-        const Wave<T>& wB = P.wB;
-        const bool f1 = wB.s1 < T(0), f2 = wB.s2 < T(0), f3 = wB.s3 < T(0);
+        T dhi[3];
+        wave_dots(in.w, wA, dhi);
+        // limited correction and fluctuations at v-3/2
         T Gm[3], Gp[3];
-        hr_split(wB,
-                 f1 ? wA.a1 : P.wC.a1, f1 ? wA.s1 : P.wC.s1, f1 ? wA.r1 : P.wC.r1,
-                 f2 ? wA.a2 : P.wC.a2, f2 ? wA.s2 : P.wC.s2, f2 ? wA.r2 : P.wC.r2,
-                 f3 ? wA.a3 : P.wC.a3, dt, Gm, Gp);
-        // stage C: x2-swept row v-2 (split-local order R, N, M)
+        hr_split(in.w, in.dlo, dhi, dt, Gm, Gp);
+        // row v-2 completes; row v-1 receives its lower flux (split-local order R, N, M)
         Cell<T> qn;
-        qn.R = fma_(-dt, Gm[0] + P.gpC[0], P.p2.R);
-        qn.N = fma_(-dt, Gm[1] + P.gpC[1], P.p2.N);
-        qn.M = fma_(-dt, Gm[2] + P.gpC[2], P.p2.M);
+        qn.R = fma_(-dt, Gm[0], in.part.R);
+        qn.N = fma_(-dt, Gm[1], in.part.N);
+        qn.M = fma_(-dt, Gm[2], in.part.M);
+        out.part.R = fma_(-dt, Gp[0], in.q.R);
+        out.part.N = fma_(-dt, Gp[1], in.q.N);
+        out.part.M = fma_(-dt, Gp[2], in.q.M);
+        if constexpr (AXI) geometric_half_step(qn, hdt * rcp(T(v - 2) + T(0.5)));
         const T irn = rcp(T(1) + qn.R);
         const T un = qn.M * irn, vn = qn.N * irn;
-        // stage D: source of row j = v-3, then store
+        // source of row j = v-3 (x2-swept rows j-1, j, j+1), then store
         const int j = v - 3;
         if (j >= r0 && j < r1) {
-            T uxl = perm(P.uc, lm1), vxl = perm(P.vc, lm1);
-            T uxr = perm(P.uc, lp1), vxr = perm(P.vc, lp1);
-            T ubl = P.ub, vbl = P.vb, uab = un, vab = vn;
-            if (!perx && col == 0) {
-                const int b = d.bc[0];
-                if (b == BC_REFLECT) { uxl = -P.uc; vxl = P.vc; }
-                else if (b == BC_TAYLOR) taylor_uv(-0.5, j + 0.5, uxl, vxl);
-                else if (b == BC_SOURCE && j + 0.5 <= d.sr_ap) {
-                    T R, M, N;
-                    source_at<T>(d, j + 0.5, tn, R, M, N);
-                    const T ir = rcp(T(1) + R);
-                    uxl = M * ir; vxl = N * ir;
-                } else { uxl = P.uc; vxl = P.vc; }
-            }
-            if (!perx && col == nx - 1) {
-                const int b = d.bc[1];
-                if (b == BC_REFLECT) { uxr = -P.uc; vxr = P.vc; }
-                else if (b == BC_TAYLOR) taylor_uv(nx + 0.5, j + 0.5, uxr, vxr);
-                else { uxr = P.uc; vxr = P.vc; }
+            T uxl = perm(in.us, lm1), vxl = perm(in.vs, lm1);
+            T uxr = perm(in.us, lp1), vxr = perm(in.vs, lp1);
+            T ubl = in.ub, vbl = in.vb, uab = un, vab = vn;
+            if (EDGE) {
+                if (ghost_lo) {
+                    const int b = d.bc[0];
+                    if (b == BC_REFLECT) { uxl = -in.us; vxl = in.vs; }
+                    else if (b == BC_TAYLOR) taylor_uv(-0.5, j + 0.5, uxl, vxl);
+                    else if (b == BC_SOURCE && j + 0.5 <= d.sr_ap) {
+                        T R, M, N;
+                        source_at<T>(d, j + 0.5, tn, R, M, N);
+                        const T ir = rcp(T(1) + R);
+                        uxl = M * ir; vxl = N * ir;
+                    } else { uxl = in.us; vxl = in.vs; }
+                }
+                if (ghost_hi) {
+                    const int b = d.bc[1];
+                    if (b == BC_REFLECT) { uxr = -in.us; vxr = in.vs; }
+                    else if (b == BC_TAYLOR) taylor_uv(nx + 0.5, j + 0.5, uxr, vxr);
+                    else { uxr = in.us; vxr = in.vs; }
+                }
             }
             if (!pery && j == 0) {
                 const int b = d.bc[2];
-                if (b == BC_REFLECT) { ubl = P.uc; vbl = -P.vc; }
+                if (b == BC_REFLECT) { ubl = in.us; vbl = -in.vs; }
                 else if (b == BC_TAYLOR) taylor_uv(col + 0.5, -0.5, ubl, vbl);
-                else { ubl = P.uc; vbl = P.vc; }
+                else { ubl = in.us; vbl = in.vs; }
             }
             if (!pery && j == ny - 1) {
                 const int b = d.bc[3];
-                if (b == BC_REFLECT) { uab = P.uc; vab = -P.vc; }
+                if (b == BC_REFLECT) { uab = in.us; vab = -in.vs; }
                 else if (b == BC_TAYLOR) taylor_uv(col + 0.5, ny + 0.5, uab, vab);
-                else { uab = P.uc; vab = P.vc; }
+                else { uab = in.us; vab = in.vs; }
             }
-            const T lapu = ((uxl + uxr) + (ubl + uab)) - T(4) * P.uc;
-            const T lapv = ((vxl + vxr) + (vbl + vab)) - T(4) * P.vc;
-            T oR = P.qc.R, oM, oN;
+            const T lapu = ((uxl + uxr) + (ubl + uab)) - T(4) * in.us;
+            const T lapv = ((vxl + vxr) + (vbl + vab)) - T(4) * in.vs;
+            const T oR = in.qs.R;
+            T oM, oN;
             if constexpr (AXI) {
-                const T r = T(j) + T(0.5);
-                const T ir = rcp(r);
+                // cylindrical vector Laplacian: + (1/r) d/dr of each velocity, - v/r^2
+                const T ir = rcp(T(j) + T(0.5));
                 const T dur = T(0.5) * (uab - ubl), dvr = T(0.5) * (vab - vbl);
-                const T sR = -P.qc.N * ir;
-                const T sM = fma_(delta, fma_(dur, ir, lapu), -P.uc * P.vc * ir);
-                const T sN = fma_(delta, fma_(-P.vc, ir * ir, fma_(dvr, ir, lapv)), -P.vc * P.vc * ir);
-                oR = fma_(dt, sR, P.qc.R);
-                oM = fma_(dt, sM, P.qc.M);
-                oN = fma_(dt, sN, P.qc.N);
+                const T k = dt * delta;
+                oM = fma_(k, fma_(dur, ir, lapu), in.qs.M);
+                oN = fma_(k, fma_(-in.vs, ir * ir, fma_(dvr, ir, lapv)), in.qs.N);
             } else {
                 const T k = dt * delta;
-                oM = fma_(k, lapu, P.qc.M);
-                oN = fma_(k, lapv, P.qc.N);
+                oM = fma_(k, lapu, in.qs.M);
+                oN = fma_(k, lapv, in.qs.N);
             }
             if (out_lane) {
                 const size_t o = (size_t)j * pitch + (size_t)col;
@@ -496,61 +588,89 @@ __device__ __forceinline__ void march(const SimDesc& d, int strip, int seg, bool
                 outN[o] = C::st(oN, is2);
             }
         }
-        // rotate
-        P.ub = P.uc; P.vb = P.vc;
-        P.qc = qn; P.uc = un; P.vc = vn;
-        P.gpC[0] = Gp[0]; P.gpC[1] = Gp[1]; P.gpC[2] = Gp[2];
-        P.wC = P.wB; P.wB = wA;
-        P.p2 = P.p1; P.p1 = q; P.pu1 = u; P.pv1 = vv;
-        if (v == ny - 2) P.stash = q;
+        out.q = q; out.u = u; out.v = vv;
+        out.w = wA;
+        out.dlo[0] = dhi[0]; out.dlo[1] = dhi[1]; out.dlo[2] = dhi[2];
+        out.qs = qn; out.us = un; out.vs = vn;
+        out.ub = in.us; out.vb = in.vs;
     };
 
-    // ghost row of the x1-swept state at the top (v >= ny, non-periodic)
-    auto top_ghost = [&](int v) -> Cell<T> {
+    Carry<T> A, B;
+    carry_zero(A);
+    carry_zero(B);
+    Cell<T> stash = {T(0), T(0), T(0)};    // x1-swept row ny-2 (reflecting top ghost)
+    auto keep = [&](const Cell<T>& q, int v) { if (v == ny - 2) stash = q; };
+
+    int v = vfirst;
+    if (!pery && r0 == 0) {
+        // bottom side: the ghost rows of the x1-swept state need rows 0 and 1 first
+        S a0, b0, c0_, a1, b1, c1;
+        load_row(0, a0, b0, c0_);
+        load_row(1, a1, b1, c1);
+        const Cell<T> q0 = xsweep(0, a0, b0, c0_);
+        const Cell<T> q1 = xsweep(1, a1, b1, c1);
+        const int b = d.bc[2];
+        Cell<T> g[HALO];
+        for (int k = HALO; k >= 1; --k) {       // rows -3, -2, -1
+            Cell<T> q;
+            if (b == BC_TAYLOR) {
+                double R, M, N;
+                taylor_at(d, col + 0.5, -k + 0.5, tn, R, M, N);
+                q.R = (T)R; q.M = (T)M; q.N = (T)N;
+            } else if (b == BC_REFLECT) {
+                q = (k == 1) ? q0 : q1;
+                q.N = -q.N;
+            } else {
+                q = q0;
+            }
+            g[k - 1] = q;
+        }
+        push(g[2], -3, A, B);
+        push(g[1], -2, B, A);
+        push(g[0], -1, A, B);
+        push(q0, 0, B, A); keep(q0, 0);
+        push(q1, 1, A, B); keep(q1, 1);
+        A = B;
+        v = 2;
+    }
+    // real rows, two per iteration, loads one row ahead
+    const int vlast = r1 + HALO - 1;
+    const int vreal = pery ? vlast : min(vlast, ny - 1);
+    auto wrap = [&](int vv) { return pery ? ((vv % ny) + ny) % ny : vv; };
+    if (v <= vreal) {
+        S na, nb, nc;
+        load_row(wrap(v), na, nb, nc);
+        for (; v + 1 <= vreal; v += 2) {
+            S a = na, b = nb, c = nc;
+            load_row(wrap(v + 1), na, nb, nc);
+            const Cell<T> q = xsweep(wrap(v), a, b, c);
+            push(q, v, A, B); keep(q, v);
+            a = na; b = nb; c = nc;
+            if (v + 2 <= vreal) load_row(wrap(v + 2), na, nb, nc);
+            const Cell<T> q2 = xsweep(wrap(v + 1), a, b, c);
+            push(q2, v + 1, B, A); keep(q2, v + 1);
+        }
+        if (v <= vreal) {
+            const Cell<T> q = xsweep(wrap(v), na, nb, nc);
+            push(q, v, A, B); keep(q, v);
+            A = B;
+            ++v;
+        }
+    }
+    // ghost rows above a non-periodic top side
+    for (; v <= vlast; ++v) {
         const int b = d.bc[3];
-        Cell<T> q = P.p1;
+        Cell<T> q = A.q;                           // zero-order extrapolation of Q*_{ny-1}
         if (b == BC_TAYLOR) {
             double R, M, N;
             taylor_at(d, col + 0.5, v + 0.5, tn, R, M, N);
             q.R = (T)R; q.M = (T)M; q.N = (T)N;
         } else if (b == BC_REFLECT) {
-            if (v == ny) { q = P.p1; q.N = -q.N; }
-            else if (v == ny + 1) { q = P.stash; q.N = -q.N; }
+            if (v == ny) { q = A.q; q.N = -q.N; }
+            else if (v == ny + 1) { q = stash; q.N = -q.N; }
         }
-        return q;
-    };
-
-    int v = vfirst;
-    if (!pery && r0 == 0) {
-        // bottom side: the ghost rows of the x1-swept state need rows 0 and 1 first
-        const Cell<T> q0 = xsweep(0);
-        const Cell<T> q1 = xsweep(1);
-        const int b = d.bc[2];
-        for (int g = HALO; g >= 1; --g) {       // rows -3, -2, -1
-            Cell<T> q;
-            if (b == BC_TAYLOR) {
-                double R, M, N;
-                taylor_at(d, col + 0.5, -g + 0.5, tn, R, M, N);
-                q.R = (T)R; q.M = (T)M; q.N = (T)N;
-            } else if (b == BC_REFLECT) {
-                q = (g == 1) ? q0 : q1;
-                q.N = -q.N;
-            } else {
-                q = q0;
-            }
-            push(q, -g);
-        }
-        push(q0, 0);
-        push(q1, 1);
-        v = 2;
-    }
-    const int vlast = r1 + HALO - 1;
-    for (; v <= vlast; ++v) {
-        Cell<T> q;
-        if (pery) q = xsweep(((v % ny) + ny) % ny);
-        else if (v < ny) q = xsweep(v);
-        else q = top_ghost(v);
-        push(q, v);
+        push(q, v, A, B);
+        A = B;
     }
 
     // ---- wave reductions: max |s| and the non-hyperbolic flag ----
@@ -558,12 +678,24 @@ __device__ __forceinline__ void march(const SimDesc& d, int strip, int seg, bool
         T m = smax;
         for (int off = 32; off >= 1; off >>= 1) m = max_(m, perm(m, lane ^ off));
         const bool anybad = __any(bad);
+        const bool anynf = __any(nonfin);
         if (lane == 0) {
-            const double md = (double)m;
+            const double md = cfl_speed<T>(m);
             atomicMax(&d.clk->smax_bits, (unsigned long long)__double_as_longlong(md));
-            if (anybad) atomicOr(&d.clk->flags, (unsigned int)FLAG_NONHYP);
+            const unsigned fl = (anybad ? FLAG_NONHYP : 0u) | (anynf ? FLAG_NONFINITE : 0u);
+            if (fl) atomicOr(&d.clk->flags, fl);
         }
     }
+}
+
+// Interior strips (no ghost column, no x override) take the lean variant.
+template <typename S, typename T, int AXI>
+__device__ __forceinline__ void march_tile(const SimDesc& d, int strip, int seg, bool count)
+{
+    const int c0 = strip * OUTW;
+    const bool interior = d.bc[0] == BC_PERIODIC || (c0 - HALO >= 0 && c0 + OUTW + HALO - 1 <= d.nx - 1);
+    if (interior) march<S, T, AXI, false>(d, strip, seg, count);
+    else march<S, T, AXI, true>(d, strip, seg, count);
 }
 
 }  // namespace fvna

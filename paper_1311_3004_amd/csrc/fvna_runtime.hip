@@ -30,21 +30,27 @@ using namespace fvna;
 // Kernels
 // ---------------------------------------------------------------------------
 
+// Waves per SIMD the register allocation must allow: four for FP32 compute
+// (measured faster than three with a few more registers), two for FP64.
+template <typename T> struct Occupancy { static constexpr int waves = sizeof(T) == 8 ? 2 : 4; };
+
 template <typename S, typename T, int AXI>
-__global__ __launch_bounds__(256) void k_step(SimDesc d, int force)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occupancy<T>::waves)))
+void k_step(SimDesc d, int force)
 {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int tile = blockIdx.x * WAVES_PER_BLOCK + wave;
     if (tile >= d.strips * d.segs) return;
     const Clock* clk = d.clk;
     if (!force && (clk->status != 0 || clk->accepted >= clk->target)) return;
-    march<S, T, AXI>(d, tile % d.strips, tile / d.strips, true);
+    march_tile<S, T, AXI>(d, tile % d.strips, tile / d.strips, true);
 }
 
 struct TileRef { int sim, strip, seg, pad; };
 
 template <typename S, typename T, int AXI>
-__global__ __launch_bounds__(256) void k_step_batch(const SimDesc* __restrict__ descs,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occupancy<T>::waves)))
+void k_step_batch(const SimDesc* __restrict__ descs,
                                                     const TileRef* __restrict__ tiles, int ntiles,
                                                     int force)
 {
@@ -52,10 +58,10 @@ __global__ __launch_bounds__(256) void k_step_batch(const SimDesc* __restrict__ 
     const int tile = blockIdx.x * WAVES_PER_BLOCK + wave;
     if (tile >= ntiles) return;
     const TileRef tr = tiles[tile];
-    const SimDesc d = descs[tr.sim];
+    const SimDesc& d = descs[tr.sim];
     const Clock* clk = d.clk;
     if (!force && (clk->status != 0 || clk->accepted >= clk->target)) return;
-    march<S, T, AXI>(d, tr.strip, tr.seg, true);
+    march_tile<S, T, AXI>(d, tr.strip, tr.seg, true);
 }
 
 // Accept or reject the attempt just made, from its largest wave speed
@@ -70,7 +76,7 @@ __device__ void control(const SimDesc& d)
     c->smax_bits = 0ull;
     c->flags = 0u;
     if (flags & FLAG_NONHYP) { c->status = ST_NONHYP; c->status_step = c->accepted; return; }
-    if (!(smax <= DBL_MAX)) { c->status = ST_NONFINITE; c->status_step = c->accepted; return; }
+    if ((flags & FLAG_NONFINITE) || !(smax <= DBL_MAX)) { c->status = ST_NONFINITE; c->status_step = c->accepted; return; }
     const double nu = c->dt * smax;
     c->nu_last = nu;
     if (!d.fixed_dt && nu > d.cfl_max) {
@@ -171,30 +177,33 @@ __global__ __launch_bounds__(256) void k_dry(SimDesc d)
     const int j = blockIdx.y;
     const double t = d.clk->t;
     const T beta = (T)d.beta;
-    T sm = T(0);
-    bool bad = false;
+    T sm = cfl_floor<T>();
+    bool bad = false, nf = false;
     if (i <= d.nx) {
+        T cfl;
         if (j < d.ny) {
             const Cell<T> a = cell_at<S, T>(d, i - 1, j, t), b = cell_at<S, T>(d, i, j, t);
             const T ia = rcp(T(1) + a.R), ib = rcp(T(1) + b.R);
             Wave<T> w;
-            bad |= !roe(a.R, a.M, a.N, a.M * ia, a.N * ia, b.R, b.M, b.N, b.M * ib, b.N * ib, beta, w);
-            sm = max_(sm, max_(abs_(w.s1), max_(abs_(w.s2), abs_(w.s3))));
+            bad |= !roe(a.R, a.M, a.N, a.M * ia, a.N * ia, b.R, b.M, b.N, b.M * ib, b.N * ib, beta, w, cfl, nf);
+            sm = max_(sm, cfl);
         }
         if (i < d.nx) {
             const Cell<T> a = cell_at<S, T>(d, i, j - 1, t), b = cell_at<S, T>(d, i, j, t);
             const T ia = rcp(T(1) + a.R), ib = rcp(T(1) + b.R);
             Wave<T> w;
-            bad |= !roe(a.R, a.N, a.M, a.N * ia, a.M * ia, b.R, b.N, b.M, b.N * ib, b.M * ib, beta, w);
-            sm = max_(sm, max_(abs_(w.s1), max_(abs_(w.s2), abs_(w.s3))));
+            bad |= !roe(a.R, a.N, a.M, a.N * ia, a.M * ia, b.R, b.N, b.M, b.N * ib, b.M * ib, beta, w, cfl, nf);
+            sm = max_(sm, cfl);
         }
     }
     const int lane = threadIdx.x & 63;
     for (int off = 32; off >= 1; off >>= 1) sm = max_(sm, perm(sm, lane ^ off));
     const bool anybad = __any(bad);
+    const bool anynf = __any(nf);
     if (lane == 0) {
-        atomicMax(&d.clk->smax_bits, (unsigned long long)__double_as_longlong((double)sm));
-        if (anybad) atomicOr(&d.clk->flags, (unsigned int)FLAG_NONHYP);
+        atomicMax(&d.clk->smax_bits, (unsigned long long)__double_as_longlong(cfl_speed<T>(sm)));
+        const unsigned fl = (anybad ? FLAG_NONHYP : 0u) | (anynf ? FLAG_NONFINITE : 0u);
+        if (fl) atomicOr(&d.clk->flags, fl);
     }
 }
 
@@ -207,7 +216,11 @@ __global__ void k_dt0(SimDesc d)
     c->smax_bits = 0ull;
     c->flags = 0u;
     if (flags & FLAG_NONHYP) { c->status = ST_NONHYP; c->status_step = 0; return; }
-    if (!(smax > 0.0) || !(smax <= DBL_MAX)) { c->status = ST_NONFINITE; c->status_step = 0; return; }
+    if ((flags & FLAG_NONFINITE) || !(smax > 0.0) || !(smax <= DBL_MAX)) {
+        c->status = ST_NONFINITE;
+        c->status_step = 0;
+        return;
+    }
     c->dt = d.cfl_target / smax;
 }
 
@@ -225,14 +238,14 @@ __global__ void k_import(SimDesc d, const double* __restrict__ src, int field, i
 }
 
 template <typename S, typename T>
-__global__ void k_export(SimDesc d, double* __restrict__ dst, int field, int row0, int nrows,
-                         double factor)
+__global__ void k_export(SimDesc d, double* __restrict__ dst, int field, int row0, int nrows, int col0,
+                         int ncols, double factor)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int r = blockIdx.y;
-    if (i >= d.nx || r >= nrows) return;
-    const S* src = (const S*)d.buf[d.clk->cur] + (size_t)field * d.plane + (size_t)(row0 + r) * d.pitch;
-    dst[(size_t)r * d.nx + i] = (double)Codec<S, T>::ld(src[i], d.scale[field]) * factor;
+    if (i >= ncols || r >= nrows) return;
+    const S* src = (const S*)d.buf[d.clk->cur] + (size_t)field * d.plane + (size_t)(row0 + r) * d.pitch + col0;
+    dst[(size_t)r * ncols + i] = (double)Codec<S, T>::ld(src[i], d.scale[field]) * factor;
 }
 
 // Fixed-order FP64 sums: block b sums rows b, b + NB, ... with a fixed
@@ -377,10 +390,28 @@ size_t scratch_bytes_of(const fvna_params* p)
     return OFF_STAGE + align_up(stage_cells_of(p) * sizeof(double), ALIGN);
 }
 
-int default_tile_rows(const fvna_params* p)
+// Rows per wavefront segment when none is given: enough segments that the
+// grid's wavefronts fill every resident slot of the device (CUs x 4 SIMDs x
+// the occupancy the step kernel is compiled for) in one round without
+// spilling a few into a second round, and never fewer than 16 rows (the six
+// warm-up rows of a segment are redundant work).
+int default_tile_rows(const fvna_params* p, int cu_count)
 {
-    (void)p;
-    return 64;
+    const int waves_per_simd = p->precision == FVNA_F64 ? 2 : 4;
+    const long long slots = (long long)std::max(cu_count, 1) * 4 * waves_per_simd;
+    const long long strips = (p->nx + OUTW - 1) / OUTW;
+    const long long per_strip = std::max(1ll, slots / strips);
+    long long tr = (p->ny + per_strip - 1) / per_strip;
+    tr = std::max(16ll, std::min(tr, 65536ll));
+    return (int)tr;
+}
+
+int device_cu_count()
+{
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) return 256;
+    return n;
 }
 
 // in-process autotune cache keyed by (precision, geometry, nx, ny)
@@ -394,7 +425,7 @@ struct Launcher {
     void (*step_batch)(const SimDesc*, const TileRef*, int ntiles, int force, hipStream_t);
     void (*dry)(const SimDesc&, hipStream_t);
     void (*imp)(const SimDesc&, const double*, int, int, int, double, int, hipStream_t);
-    void (*exp)(const SimDesc&, double*, int, int, int, double, hipStream_t);
+    void (*exp)(const SimDesc&, double*, int, int, int, int, int, double, hipStream_t);
     void (*sums)(const SimDesc&, double*, hipStream_t);
 };
 
@@ -419,9 +450,10 @@ Launcher make_launcher()
         hipLaunchKernelGGL((k_import<S, T>), dim3((d.pitch + 255) / 256, nrows), dim3(256), 0, s, d, src, field,
                            row0, nrows, denom, buf);
     };
-    L.exp = [](const SimDesc& d, double* dst, int field, int row0, int nrows, double factor, hipStream_t s) {
-        hipLaunchKernelGGL((k_export<S, T>), dim3((d.nx + 255) / 256, nrows), dim3(256), 0, s, d, dst, field, row0,
-                           nrows, factor);
+    L.exp = [](const SimDesc& d, double* dst, int field, int row0, int nrows, int col0, int ncols, double factor,
+               hipStream_t s) {
+        hipLaunchKernelGGL((k_export<S, T>), dim3((ncols + 255) / 256, nrows), dim3(256), 0, s, d, dst, field, row0,
+                           nrows, col0, ncols, factor);
     };
     L.sums = [](const SimDesc& d, double* part, hipStream_t s) {
         hipLaunchKernelGGL((k_sums_partial<S, T>), dim3(SUM_BLOCKS), dim3(256), 0, s, d, part);
@@ -580,7 +612,7 @@ fvna_status fvna_create(const fvna_params* p, void* state_a, void* state_b, void
     if (tr == 0) {
         std::lock_guard<std::mutex> g(g_tune_mu);
         auto it = g_tune.find(std::make_tuple(p->precision, p->geometry, p->nx, p->ny));
-        tr = it != g_tune.end() ? it->second : default_tile_rows(p);
+        tr = it != g_tune.end() ? it->second : default_tile_rows(p, device_cu_count());
     }
     fill_desc(c->d, p, state_a, state_b, c->clk, tr);
     if (hipGetDevice(&c->device) != hipSuccess ||
@@ -686,18 +718,28 @@ fvna_status fvna_set_clock(fvna_ctx* c, double t, double dt_next)
     return reset_clock(c, t * p.c0 / p.dx, dt_next > 0 ? dt_next * p.c0 / p.dx : 0.0, h.cur);
 }
 
+// Enqueue exactly `attempts` attempts: whole captured chunks, then single launches.
+static fvna_status enqueue_attempts(fvna_ctx* c, long long attempts)
+{
+    fvna_status s = build_graph(c);
+    if (s) return s;
+    for (long long k = 0; k < attempts / GRAPH_CHUNK; ++k) HIP_TRY(hipGraphLaunch(c->exec, c->stream));
+    for (long long k = 0; k < attempts % GRAPH_CHUNK; ++k) {
+        c->L.step(c->d, 0, c->stream);
+        hipLaunchKernelGGL(k_ctrl, dim3(1), dim3(64), 0, c->stream, c->d);
+    }
+    HIP_TRY(hipGetLastError());
+    return FVNA_OK;
+}
+
 fvna_status fvna_step(fvna_ctx* c, int64_t nsteps)
 {
     if (!c) return fail(FVNA_E_INVALID, "ctx is NULL");
     if (nsteps < 0) return fail(FVNA_E_INVALID, "nsteps must be >= 0");
     if (nsteps == 0) return FVNA_OK;
-    fvna_status s = build_graph(c);
-    if (s) return s;
     hipLaunchKernelGGL(k_bump, dim3(1), dim3(64), 0, c->stream, c->clk, (long long)nsteps);
     HIP_TRY(hipGetLastError());
-    const int64_t launches = (nsteps + GRAPH_CHUNK - 1) / GRAPH_CHUNK;
-    for (int64_t k = 0; k < launches; ++k) HIP_TRY(hipGraphLaunch(c->exec, c->stream));
-    return FVNA_OK;
+    return enqueue_attempts(c, nsteps);
 }
 
 fvna_status fvna_sync(fvna_ctx* c)
@@ -709,34 +751,38 @@ fvna_status fvna_sync(fvna_ctx* c)
         if (s) return s;
         if (h.status != 0 || h.accepted >= h.target) return status_of(h.status);
         // rejected attempts left steps owed: run more attempts
-        const long long owed = h.target - h.accepted;
-        s = build_graph(c);
+        s = enqueue_attempts(c, h.target - h.accepted);
         if (s) return s;
-        const long long launches = (owed + GRAPH_CHUNK - 1) / GRAPH_CHUNK;
-        for (long long k = 0; k < launches; ++k) HIP_TRY(hipGraphLaunch(c->exec, c->stream));
     }
     return fail(FVNA_E_STATE, "steps still owed after many top-up rounds");
 }
 
-// Copy the current state of a context out (no synchronisation of owed steps).
-static fvna_status export_state(fvna_ctx* c, double* rho_p, double* mom_x, double* mom_y)
+// Copy a window of the current state of a context out (no synchronisation of
+// owed steps).
+static fvna_status export_window(fvna_ctx* c, int i0, int j0, int ni, int nj, double* rho_p, double* mom_x,
+                                 double* mom_y)
 {
     const fvna_params& p = c->p;
     double* stage = (double*)(c->scratch + OFF_STAGE);
-    const size_t chunk_rows = std::max<size_t>(1, stage_cells_of(&p) / (size_t)p.nx);
+    const size_t chunk_rows = std::max<size_t>(1, stage_cells_of(&p) / (size_t)ni);
     const double factor[3] = {p.rho0, p.rho0 * p.c0, p.rho0 * p.c0};
     double* dst[3] = {rho_p, mom_x, mom_y};
     HIP_TRY(hipStreamSynchronize(c->stream));
     for (int f = 0; f < 3; ++f)
-        for (size_t r0 = 0; r0 < (size_t)p.ny; r0 += chunk_rows) {
-            const size_t nr = std::min(chunk_rows, (size_t)p.ny - r0);
-            c->L.exp(c->d, stage, f, (int)r0, (int)nr, factor[f], c->stream);
+        for (size_t r0 = 0; r0 < (size_t)nj; r0 += chunk_rows) {
+            const size_t nr = std::min(chunk_rows, (size_t)nj - r0);
+            c->L.exp(c->d, stage, f, (int)(j0 + r0), (int)nr, i0, ni, factor[f], c->stream);
             HIP_TRY(hipGetLastError());
-            HIP_TRY(hipMemcpyAsync(dst[f] + r0 * (size_t)p.nx, stage, nr * (size_t)p.nx * sizeof(double),
+            HIP_TRY(hipMemcpyAsync(dst[f] + r0 * (size_t)ni, stage, nr * (size_t)ni * sizeof(double),
                                    hipMemcpyDeviceToHost, c->stream));
             HIP_TRY(hipStreamSynchronize(c->stream));
         }
     return FVNA_OK;
+}
+
+static fvna_status export_state(fvna_ctx* c, double* rho_p, double* mom_x, double* mom_y)
+{
+    return export_window(c, 0, 0, c->p.nx, c->p.ny, rho_p, mom_x, mom_y);
 }
 
 static fvna_status stats_of(fvna_ctx* c, fvna_stats* st)
@@ -769,6 +815,21 @@ fvna_status fvna_get_state(fvna_ctx* c, double* rho_p, double* mom_x, double* mo
     if (dev != FVNA_OK && !is_device_error(dev)) return dev;
     const std::string msg = g_err;
     fvna_status s = export_state(c, rho_p, mom_x, mom_y);
+    if (s) return s;
+    if (dev != FVNA_OK) g_err = msg;
+    return dev;
+}
+
+fvna_status fvna_get_window(fvna_ctx* c, int32_t i0, int32_t j0, int32_t ni, int32_t nj, double* rho_p,
+                            double* mom_x, double* mom_y)
+{
+    if (!c || !rho_p || !mom_x || !mom_y) return fail(FVNA_E_INVALID, "NULL argument");
+    if (ni < 1 || nj < 1 || i0 < 0 || j0 < 0 || (long long)i0 + ni > c->p.nx || (long long)j0 + nj > c->p.ny)
+        return fail(FVNA_E_INVALID, "window outside the grid");
+    const fvna_status dev = fvna_sync(c);
+    if (dev != FVNA_OK && !is_device_error(dev)) return dev;
+    const std::string msg = g_err;
+    fvna_status s = export_window(c, i0, j0, ni, nj, rho_p, mom_x, mom_y);
     if (s) return s;
     if (dev != FVNA_OK) g_err = msg;
     return dev;
@@ -833,7 +894,19 @@ fvna_status fvna_get_tile_rows(fvna_ctx* c, int32_t* tile_rows)
 fvna_status fvna_autotune(fvna_ctx* c, int32_t* tile_rows)
 {
     if (!c) return fail(FVNA_E_INVALID, "ctx is NULL");
-    static const int cand[] = {16, 24, 32, 48, 64, 96, 128, 192, 256};
+    // candidates: segments that fill the device in 1, 2 or 3 whole rounds, and
+    // a few fixed heights
+    std::vector<int> cand = {32, 48, 64, 96, 128};
+    {
+        const int w = c->p.precision == FVNA_F64 ? 2 : 4;
+        const long long slots = (long long)device_cu_count() * 4 * w;
+        const long long strips = c->d.strips;
+        for (int rounds = 1; rounds <= 3; ++rounds) {
+            const long long per = std::max(1ll, rounds * slots / strips);
+            const long long tr = (c->p.ny + per - 1) / per;
+            if (tr >= 16) cand.push_back((int)tr);
+        }
+    }
     double best = 1e30;
     int best_tr = c->d.tile_rows;
     for (int tr : cand) {
@@ -946,7 +1019,8 @@ fvna_status fvna_batch_create(int32_t n, const fvna_params* per_sim, void* const
         const fvna_params& p = per_sim[k];
         b->p.push_back(p);
         SimDesc d;
-        int tr = p.tile_rows ? p.tile_rows : default_tile_rows(&p);
+        // many simulations fill the device in many rounds: moderate segments
+        int tr = p.tile_rows ? p.tile_rows : 96;
         char* sc = (char*)bufs[3 * k + 2];
         fill_desc(d, &p, bufs[3 * k], bufs[3 * k + 1], (Clock*)(sc + OFF_CLOCK), tr);
         b->d.push_back(d);
@@ -1000,19 +1074,28 @@ fvna_status fvna_batch_set_state(fvna_batch* b, int32_t k, const double* rho_p, 
     return fvna_set_state(&c, rho_p, mom_x, mom_y);
 }
 
+static fvna_status batch_enqueue(fvna_batch* b, long long attempts)
+{
+    fvna_status s = batch_graph(b);
+    if (s) return s;
+    for (long long k = 0; k < attempts / GRAPH_CHUNK; ++k) HIP_TRY(hipGraphLaunch(b->exec, b->stream));
+    for (long long k = 0; k < attempts % GRAPH_CHUNK; ++k) {
+        b->L.step_batch(b->d_desc, b->d_tiles, b->ntiles, 0, b->stream);
+        hipLaunchKernelGGL(k_ctrl_batch, dim3((b->n + 63) / 64), dim3(64), 0, b->stream, b->d_desc, b->n);
+    }
+    HIP_TRY(hipGetLastError());
+    return FVNA_OK;
+}
+
 fvna_status fvna_batch_step(fvna_batch* b, int64_t nsteps)
 {
     if (!b) return fail(FVNA_E_INVALID, "batch is NULL");
     if (nsteps < 0) return fail(FVNA_E_INVALID, "nsteps must be >= 0");
     if (nsteps == 0) return FVNA_OK;
-    fvna_status s = batch_graph(b);
-    if (s) return s;
     hipLaunchKernelGGL(k_bump_batch, dim3((b->n + 63) / 64), dim3(64), 0, b->stream, b->d_desc, b->n,
                        (long long)nsteps);
     HIP_TRY(hipGetLastError());
-    const int64_t launches = (nsteps + GRAPH_CHUNK - 1) / GRAPH_CHUNK;
-    for (int64_t k = 0; k < launches; ++k) HIP_TRY(hipGraphLaunch(b->exec, b->stream));
-    return FVNA_OK;
+    return batch_enqueue(b, nsteps);
 }
 
 fvna_status fvna_batch_sync(fvna_batch* b)
@@ -1029,10 +1112,8 @@ fvna_status fvna_batch_sync(fvna_batch* b)
             else owed = std::max(owed, h.target - h.accepted);
         }
         if (owed <= 0) return status_of(worst);
-        fvna_status s = batch_graph(b);
+        fvna_status s = batch_enqueue(b, owed);
         if (s) return s;
-        const long long launches = (owed + GRAPH_CHUNK - 1) / GRAPH_CHUNK;
-        for (long long k = 0; k < launches; ++k) HIP_TRY(hipGraphLaunch(b->exec, b->stream));
     }
     return fail(FVNA_E_STATE, "steps still owed after many top-up rounds");
 }

@@ -1,0 +1,82 @@
+"""Diagnostics of a running simulation: on-axis probes, focal peak, harmonics
+and shock-front position (the quantities the paper reads off its focused-wave
+runs: on-axis pressure maxima and the spectrum at a point, Sec. 4.2).
+
+Everything here post-processes states the library hands out through
+fvna_get_window; none of it is part of the time step.
+"""
+import math
+
+import numpy as np
+
+
+def record_row(sim, total_steps, tail_time, row=0, margin=1.15):
+    """Advance `sim` to `total_steps` accepted steps (counted from its current
+    state) and sample row `row` of p' = c0^2 rho' after every step of the final
+    `tail_time` seconds.  Returns (t [n], p [n, nx]) with t the sample times."""
+    p = sim.params
+    c2 = p.c0 * p.c0
+    st = sim.fvna_get_stats()
+    dt = st["dt_next"]
+    n_tail = min(total_steps, int(math.ceil(margin * tail_time / dt)) + 2)
+    sim.fvna_step(total_steps - n_tail)
+    ts, ps = [], []
+    for _ in range(n_tail):
+        sim.fvna_step(1)
+        rp, _, _ = sim.fvna_get_window(0, row, p.nx, 1)
+        ts.append(sim.fvna_get_stats()["t"])
+        ps.append(rp[0] * c2)
+    t = np.array(ts)
+    P = np.array(ps)
+    keep = t >= t[-1] - tail_time * (1 + 1e-9)
+    return t[keep], P[keep]
+
+
+def harmonics(t, p, freq, n=5):
+    """Amplitudes of harmonics 1..n of p(t) over the sampled window by a
+    nonuniform DFT (trapezoidal weights), assuming the window spans an integer
+    number of periods of `freq`."""
+    t = np.asarray(t)
+    w = np.empty_like(t)
+    w[1:-1] = 0.5 * (t[2:] - t[:-2])
+    w[0] = 0.5 * (t[1] - t[0])
+    w[-1] = 0.5 * (t[-1] - t[-2])
+    T = t[-1] - t[0]
+    out = []
+    for k in range(1, n + 1):
+        e = np.exp(-2j * np.pi * k * freq * t)
+        out.append(abs(2.0 / T * np.sum(w * p * e)))
+    return np.array(out)
+
+
+def focal_summary(t, P, freq, dx, n_harm=5, zstar=None):
+    """p+ and p- per axial cell over the window, the focal cell (largest p+)
+    and the harmonics there."""
+    pplus = P.max(axis=0)
+    pminus = P.min(axis=0)
+    k = int(np.argmax(pplus)) if zstar is None else int(zstar)
+    return {"z_index": k, "z_m": (k + 0.5) * dx, "p_plus": float(pplus[k]), "p_minus": float(pminus[k]),
+            "p_plus_axis": pplus, "p_minus_axis": pminus,
+            "harmonics": harmonics(t, P[:, k], freq, n_harm)}
+
+
+def shock_front(p_row, center, half_width):
+    """Sub-cell position of the steepest compression front (largest -dp/dz)
+    of an axial pressure profile within [center - half_width, center + half_width],
+    refined by a parabola through the three largest-gradient samples."""
+    g = -(p_row[1:] - p_row[:-1])                 # at faces k + 1/2 (cell units, k = 0..)
+    lo = max(1, center - half_width)
+    hi = min(len(g) - 1, center + half_width)
+    k = lo + int(np.argmax(g[lo:hi]))
+    y0, y1, y2 = g[k - 1], g[k], g[k + 1]
+    den = y0 - 2 * y1 + y2
+    off = 0.5 * (y0 - y2) / den if den != 0 else 0.0
+    return k + 1.0 + off                         # face k + 1/2 sits at cell coordinate k + 1
+
+
+def compare(a, b):
+    """Relative differences of focal quantities of run a against reference b."""
+    h = np.abs(a["harmonics"] - b["harmonics"]) / np.maximum(b["harmonics"], 1e-300)
+    return {"p_plus_rel": abs(a["p_plus"] - b["p_plus"]) / abs(b["p_plus"]),
+            "p_minus_rel": abs(a["p_minus"] - b["p_minus"]) / abs(b["p_minus"]),
+            "harmonics_rel": [float(x) for x in h]}

@@ -12,7 +12,7 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libfvna.so")
+LIB_PATH = os.environ.get("FVNA_LIB") or os.path.join(_HERE, "libfvna.so")
 
 OK, E_INVALID, E_NOMEM, E_HIP, E_NONHYPERBOLIC, E_NONFINITE, E_RETRIES, E_STATE = range(8)
 CARTESIAN, AXISYMMETRIC = 0, 1
@@ -26,7 +26,7 @@ BCS = {"periodic": BC_PERIODIC, "extrap0": BC_EXTRAP0, "reflect": BC_REFLECT,
 
 EXPORTS = [
     "fvna_workspace_size", "fvna_create", "fvna_set_bc", "fvna_set_source", "fvna_set_taylor",
-    "fvna_set_state", "fvna_set_clock", "fvna_step", "fvna_sync", "fvna_get_state",
+    "fvna_set_state", "fvna_set_clock", "fvna_step", "fvna_sync", "fvna_get_state", "fvna_get_window",
     "fvna_get_stats", "fvna_sums", "fvna_time_step_kernel", "fvna_autotune", "fvna_get_tile_rows",
     "fvna_last_error", "fvna_destroy", "fvna_batch_create", "fvna_batch_set_state",
     "fvna_batch_step", "fvna_batch_sync", "fvna_batch_get_state", "fvna_batch_get_stats",
@@ -82,6 +82,7 @@ def _load():
         "fvna_step": (st, [vp, i64]),
         "fvna_sync": (st, [vp]),
         "fvna_get_state": (st, [vp, dp, dp, dp]),
+        "fvna_get_window": (st, [vp, i32, i32, i32, i32, dp, dp, dp]),
         "fvna_get_stats": (st, [vp, P(fvna_stats)]),
         "fvna_sums": (st, [vp, dp]),
         "fvna_time_step_kernel": (st, [vp, i32, dp]),
@@ -216,6 +217,13 @@ class Sim:
         out = [np.empty(self.shape, dtype=np.float64) for _ in range(3)]
         allow = (E_NONHYPERBOLIC, E_NONFINITE, E_RETRIES) if allow_device_errors else ()
         check(lib.fvna_get_state(self.handle, *[_dptr(a) for a in out]), allow)
+        return tuple(out)
+
+    def fvna_get_window(self, i0, j0, ni, nj, allow_device_errors=False):
+        out = [np.empty((int(nj), int(ni)), dtype=np.float64) for _ in range(3)]
+        allow = (E_NONHYPERBOLIC, E_NONFINITE, E_RETRIES) if allow_device_errors else ()
+        check(lib.fvna_get_window(self.handle, int(i0), int(j0), int(ni), int(nj),
+                                  *[_dptr(a) for a in out]), allow)
         return tuple(out)
 
     def fvna_get_stats(self, allow_device_errors=False):

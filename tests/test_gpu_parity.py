@@ -235,5 +235,30 @@ def test_fp32_against_fp64_gaussian_512():
     a, sa, _ = run_gpu(w, 300, "f64")
     b, sb, _ = run_gpu(w, 300, "f32")
     err = float(np.max(np.abs(a[0] - b[0])) / np.max(np.abs(a[0])))
-    _say(f"  fp32 max |dp|/p_peak {err:.3e}")
+    _say(f"  fp32 max |dp|/p_peak {err:.3e}, t rel diff {abs(sa['t'] - sb['t']) / sa['t']:.2e}")
     assert err <= 1e-5
+    # the FP32 kernel hands the CFL controller its speeds to ~1e-10, so both
+    # paths take the same steps in time
+    assert abs(sa["t"] - sb["t"]) <= 1e-8 * sa["t"]
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_axisymmetric_noise_bounded_at_cfl_099(precision):
+    """Grid-scale noise on an axisymmetric grid stays bounded at CFL 0.99
+    (the geometric terms are placed symmetrically around the x2 sweep)."""
+    from paper_1311_3004_amd import fvna
+    rng = np.random.default_rng(1)
+    nx, ny, amp = 128, 48, 1e-6
+    med = {"c0": 1500.0, "rho0": 1000.0, "beta": 3.5, "delta": 0.0}
+    st = [amp * rng.uniform(-1, 1, (ny, nx)) * f for f in (1000.0, 1.5e6, 1.5e6)]
+    dx = 1e-4
+    _say(f"case: axisymmetric noise {precision}")
+    p = fvna.make_params(nx, ny, dx, med, bc=("periodic", "periodic", "reflect", "extrap0"),
+                         geometry="axisym", precision=precision, fixed_dt=True,
+                         dt0=0.99 * dx / med["c0"])
+    s = fvna.Sim(p)
+    s.fvna_set_state(*st)
+    for _ in range(4):
+        s.fvna_step(1000)
+        R = s.fvna_get_state()[0] / med["rho0"]
+        assert np.max(np.abs(R)) < 2 * amp
