@@ -27,6 +27,34 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_CELL = {"f64": 48, "f32": 24, "f32_f16store": 12, "f32_bf16store": 12}
 
+# HBM bytes per launch of the FP32 step kernel on this workload, from two
+# rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE), each scaled by what the
+# same counter reads for a plain 1 GiB device copy (fetch x2.000, write x1.000);
+# profiles/k_step_f32_gaussian4096.md.  Valid only for the kernel sources
+# whose SHA-256 is recorded here: any other source reports traffic null.
+PMC_TRAFFIC = {
+    "bytes_per_launch": 255.4e6 + 210.3e6,
+    "fetch_bytes": 255.4e6, "write_bytes": 210.3e6,
+    "nx": 4096, "ny": 4096,
+    "sources": {
+        "fvna_device.hpp": "ae8039814e8ec79db5ea5af544ac6f6ae41e8f3453e864021d49591a48405498",
+        "fvna_runtime.hip": "e05d0474235599fd40f4f7c06913478370270e23240efefa1c31dc63f561d18a",
+    },
+}
+
+
+def measured_traffic(nx, ny):
+    """PMC bytes per launch if the kernel sources and grid are the profiled ones."""
+    import hashlib
+    if (nx, ny) != (PMC_TRAFFIC["nx"], PMC_TRAFFIC["ny"]):
+        return None
+    for name, digest in PMC_TRAFFIC["sources"].items():
+        path = os.path.join(ROOT, "paper_1311_3004_amd", "csrc", name)
+        with open(path, "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != digest:
+                return None
+    return PMC_TRAFFIC["bytes_per_launch"]
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -207,7 +235,7 @@ def main():
                    "steps": args.steps, "boundaries": "zero-order extrapolation", "seed": 2,
                    "cfl_target": 0.9, "tile_rows": tile_rows},
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(w["nx"], w["ny"]),
                      "kernel": "k_step<float,float,0>", "kernel_ms": round(ms_k, 4),
                      "bytes_per_launch": BYTES_PER_CELL["f32"] * cells},
         "wall_s": round(r32["wall_s"], 4),

@@ -30,51 +30,19 @@ using namespace fvna;
 // Kernels
 // ---------------------------------------------------------------------------
 
-// Waves per SIMD the register allocation must allow: four for FP32 compute
-// (measured faster than three with a few more registers), two for FP64.
-template <typename T> struct Occupancy { static constexpr int waves = sizeof(T) == 8 ? 2 : 4; };
-
-template <typename S, typename T, int AXI>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occupancy<T>::waves)))
-void k_step(SimDesc d, int force)
-{
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int tile = blockIdx.x * WAVES_PER_BLOCK + wave;
-    if (tile >= d.strips * d.segs) return;
-    const Clock* clk = d.clk;
-    if (!force && (clk->status != 0 || clk->accepted >= clk->target)) return;
-    march_tile<S, T, AXI>(d, tile % d.strips, tile / d.strips, true);
-}
-
-struct TileRef { int sim, strip, seg, pad; };
-
-template <typename S, typename T, int AXI>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occupancy<T>::waves)))
-void k_step_batch(const SimDesc* __restrict__ descs,
-                                                    const TileRef* __restrict__ tiles, int ntiles,
-                                                    int force)
-{
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int tile = blockIdx.x * WAVES_PER_BLOCK + wave;
-    if (tile >= ntiles) return;
-    const TileRef tr = tiles[tile];
-    const SimDesc& d = descs[tr.sim];
-    const Clock* clk = d.clk;
-    if (!force && (clk->status != 0 || clk->accepted >= clk->target)) return;
-    march_tile<S, T, AXI>(d, tr.strip, tr.seg, true);
-}
-
 // Accept or reject the attempt just made, from its largest wave speed
 // (CFL control of Sec. 4 opening; rejection rule as stated in include/fvna.h).
+// Runs in its own launch after the step kernel, on one thread per simulation.
+// (Deciding in the step kernel's last wavefront instead needs an agent-scope
+// release fence in every wavefront, which writes back the L2 and cost more
+// than the launch it saves.)
 __device__ void control(const SimDesc& d)
 {
     Clock* c = d.clk;
     if (c->status != 0 || c->accepted >= c->target) return;
     c->attempts++;
-    const double smax = __longlong_as_double((long long)c->smax_bits);
-    const unsigned flags = c->flags;
-    c->smax_bits = 0ull;
-    c->flags = 0u;
+    const double smax = __longlong_as_double((long long)atomicExch(&c->smax_bits, 0ull));
+    const unsigned flags = atomicExch(&c->flags, 0u);
     if (flags & FLAG_NONHYP) { c->status = ST_NONHYP; c->status_step = c->accepted; return; }
     if ((flags & FLAG_NONFINITE) || !(smax <= DBL_MAX)) { c->status = ST_NONFINITE; c->status_step = c->accepted; return; }
     const double nu = c->dt * smax;
@@ -105,6 +73,40 @@ __global__ void k_ctrl_batch(const SimDesc* __restrict__ descs, int n)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k < n) control(descs[k]);
+}
+
+// Waves per SIMD the register allocation must allow: four for FP32 compute
+// (measured faster than three with a few more registers), two for FP64.
+template <typename T> struct Occupancy { static constexpr int waves = sizeof(T) == 8 ? 2 : 4; };
+
+// One attempted step over the whole grid.  force = 1 (timing): run even when
+// no step is owed.
+template <typename S, typename T, int AXI>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occupancy<T>::waves)))
+void k_step(SimDesc d, int force)
+{
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tile = blockIdx.x * WAVES_PER_BLOCK + wave;
+    if (tile >= d.strips * d.segs) return;
+    const Clock* clk = d.clk;
+    if (!force && (clk->status != 0 || clk->accepted >= clk->target)) return;
+    march_tile<S, T, AXI>(d, tile % d.strips, tile / d.strips, true);
+}
+
+struct TileRef { int sim, strip, seg, pad; };
+
+template <typename S, typename T, int AXI>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occupancy<T>::waves)))
+void k_step_batch(const SimDesc* __restrict__ descs, const TileRef* __restrict__ tiles, int ntiles, int force)
+{
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tile = blockIdx.x * WAVES_PER_BLOCK + wave;
+    if (tile >= ntiles) return;
+    const TileRef tr = tiles[tile];
+    const SimDesc& d = descs[tr.sim];
+    const Clock* clk = d.clk;
+    if (!force && (clk->status != 0 || clk->accepted >= clk->target)) return;
+    march_tile<S, T, AXI>(d, tr.strip, tr.seg, true);
 }
 
 __global__ void k_bump(Clock* c, long long n)

@@ -10,6 +10,10 @@ import ctypes
 import os
 
 import numpy as np
+# torch first: its HIP runtime must be the one libfvna binds to (a library
+# loaded before torch would pull in a second HIP runtime, whose streams and
+# context torch cannot share)
+import torch  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("FVNA_LIB") or os.path.join(_HERE, "libfvna.so")

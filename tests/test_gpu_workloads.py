@@ -1,0 +1,183 @@
+"""Full-size workloads on the GPU, in the launch configuration bench.py times.
+
+* gaussian-pulse 4096^2: FP64 and FP32 against the oracle on the full grid
+  for two steps (every output element compared), FP32 against FP64 after
+  2000 steps (max |dp|/p_peak).
+* batch of uneven simulations: one batched launch per step is bitwise equal
+  to separate contexts; the autotuner changes speed, never results.
+* hifu-axisym 8192x2048 (20000 steps): FP32, FP16- and BF16-storage against
+  the FP64 GPU path -- focal peak p+/p-, harmonics 1..5 at the focal cell over
+  the final 5 cycles, shock-front position.  Tolerances are the measured
+  errors with a margin; the FP64 path itself is held to the oracle by
+  test_gpu_parity.py.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from common import max_rel, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gaussian():
+    from paper_1311_3004_amd import inputs
+    return inputs.c2_pulse_fp32(4096, 4096)
+
+
+DT_FULL = 0.9 * 1e-4 / 1500.0 / 1.001
+
+
+@pytest.fixture(scope="module")
+def gaussian_oracle(orc, gaussian):
+    _say("case: oracle, gaussian 4096^2, 2 steps (CPU)")
+    o, info = run_oracle(orc, gaussian, 2, fixed_dt=True, dt_si=DT_FULL)
+    assert info["status"] == 0
+    return o
+
+
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-12), ("f32", 2e-6)])
+def test_gaussian_4096_two_steps_vs_oracle(gaussian, gaussian_oracle, precision, tol):
+    from paper_1311_3004_amd import fvna
+    w = gaussian
+    med = w["medium"]
+    _say(f"case: gaussian 4096^2 {precision} 2 steps vs oracle (fixed dt)")
+    s = fvna.sim_from_workload(w, precision=precision, fixed_dt=True, dt0=DT_FULL)
+    s.fvna_step(2)
+    rp, mx, my = s.fvna_get_state()
+    g = (rp / med["rho0"], mx / (med["rho0"] * med["c0"]), my / (med["rho0"] * med["c0"]))
+    err = max_rel(g, gaussian_oracle)
+    _say(f"  max rel err {err:.3e}")
+    assert err <= tol
+    s.fvna_destroy()
+
+
+def test_gaussian_4096_fp32_vs_fp64_2000_steps(gaussian):
+    from paper_1311_3004_amd import fvna
+    w = gaussian
+    out = {}
+    for prec in ("f64", "f32"):
+        _say(f"case: gaussian 4096^2 {prec} 2000 adaptive steps")
+        s = fvna.sim_from_workload(w, precision=prec)
+        s.fvna_step(2000)
+        out[prec] = (s.fvna_get_state()[0], s.fvna_get_stats())
+        s.fvna_destroy()
+    a, sa = out["f64"]
+    b, sb = out["f32"]
+    err = float(np.max(np.abs(a - b)) / np.max(np.abs(a)))
+    _say(f"  fp32 max |dp|/p_peak {err:.3e}")
+    assert sa["steps"] == sb["steps"] == 2000
+    assert abs(sa["t"] - sb["t"]) <= 1e-8 * sa["t"]
+    assert err <= 2e-5
+
+
+def _batch_sims():
+    from paper_1311_3004_amd import inputs
+    rng = np.random.default_rng(44)
+    sims = []
+    for k, (nx, ny) in enumerate([(300, 260), (517, 129), (64, 400), (1000, 96), (133, 133), (257, 511)]):
+        med = dict(inputs.WATER, beta=float(rng.uniform(3, 5)), delta=float(10 ** rng.uniform(-6, -5)))
+        med, rp, mx, my, c = inputs.gaussian_pulse(nx, ny, 1e-4, float(rng.uniform(0.1e6, 5e6)), 20.0, 0.0,
+                                                   medium=med, rng=rng)
+        sims.append({"nx": nx, "ny": ny, "dx": 1e-4, "medium": med, "state": (rp, mx, my),
+                     "bc": ("extrap0", "reflect", "periodic", "periodic") if k % 2 else ("extrap0",) * 4})
+    return sims
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_batched_equals_separate_contexts_bitwise(precision):
+    from paper_1311_3004_amd import fvna
+    sims = _batch_sims()
+    plist = [fvna.make_params(x["nx"], x["ny"], x["dx"], x["medium"], bc=x["bc"], precision=precision,
+                              tile_rows=[16, 40, 96][k % 3]) for k, x in enumerate(sims)]
+    _say(f"case: batch of {len(sims)} {precision}")
+    B = fvna.Batch(plist)
+    for k, x in enumerate(sims):
+        B.fvna_batch_set_state(k, *x["state"])
+    B.fvna_batch_step(60)
+    B.fvna_batch_sync()
+    for k, x in enumerate(sims):
+        s = fvna.Sim(fvna.make_params(x["nx"], x["ny"], x["dx"], x["medium"], bc=x["bc"], precision=precision))
+        s.fvna_set_state(*x["state"])
+        s.fvna_step(60)
+        a = s.fvna_get_state()
+        b = B.fvna_batch_get_state(k)
+        sa, sb = s.fvna_get_stats(), B.fvna_batch_get_stats(k)
+        assert sa["steps"] == sb["steps"] == 60 and sa["t"] == sb["t"]
+        for u, v in zip(a, b):
+            assert np.array_equal(u, v)
+        s.fvna_destroy()
+    B.fvna_batch_destroy()
+
+
+def test_autotune_changes_speed_not_results():
+    from paper_1311_3004_amd import fvna, inputs
+    w = inputs.c2_pulse_fp32(1024, 768)
+    _say("case: autotune")
+    a = fvna.sim_from_workload(w, precision="f32", tile_rows=24)
+    a.fvna_step(40)
+    ra = a.fvna_get_state()
+    b = fvna.sim_from_workload(w, precision="f32")
+    tr = b.fvna_autotune()
+    assert tr == b.fvna_get_tile_rows() and tr >= 16
+    b.fvna_step(40)
+    rb = b.fvna_get_state()
+    for u, v in zip(ra, rb):
+        assert np.array_equal(u, v)
+
+
+@pytest.fixture(scope="module")
+def hifu_runs():
+    """The hifu-axisym 8192x2048 workload (0.2 MPa) in every precision."""
+    from paper_1311_3004_amd import fvna, inputs, diagnostics as dg
+    w = inputs.c3_hifu_fp32()
+    med, src = w["medium"], w["source"]
+    a = src["p_surface"] / (med["rho0"] * med["c0"] ** 2)
+    res = {}
+    for prec in ("f64", "f32", "f32_f16store", "f32_bf16store"):
+        _say(f"case: hifu-axisym 8192x2048 {prec} 20000 steps")
+        over = {"store_scale": (64 * a,) * 3} if "store" in prec else {}
+        s = fvna.sim_from_workload(w, precision=prec, **over)
+        t, P = dg.record_row(s, w["steps"], 5.0 / src["freq"])
+        st = s.fvna_get_stats()
+        row = s.fvna_get_window(0, 0, w["nx"], 1)[0][0] * med["c0"] ** 2
+        s.fvna_destroy()
+        assert st["status"] == 0 and st["steps"] == w["steps"]
+        res[prec] = (t, P, row, st)
+    return w, res
+
+
+def _focal(w, res, prec, zstar=None):
+    from paper_1311_3004_amd import diagnostics as dg
+    t, P, row, st = res[prec]
+    f = dg.focal_summary(t, P, w["source"]["freq"], w["dx"], zstar=zstar)
+    f["front"] = dg.shock_front(row, f["z_index"], 300)
+    return f
+
+
+@pytest.mark.parametrize("prec,tol_peak,tol_h,tol_front", [
+    ("f32", 1e-4, [1e-4, 1e-3, 1e-3, 1e-3, 5e-3], 0.05),
+    ("f32_f16store", 5e-3, [5e-3, 2e-2, 5e-2, 0.2, 0.3], 1.0),
+    ("f32_bf16store", 5e-2, [0.3, 0.6, 2.0, 5.0, 5.0], 8.0),
+])
+def test_hifu_axisym_precisions_against_fp64(hifu_runs, prec, tol_peak, tol_h, tol_front):
+    from paper_1311_3004_amd import diagnostics as dg
+    w, res = hifu_runs
+    ref = _focal(w, res, "f64")
+    # the focused field: pre-focal peak with gain well above 10 and p+ > |p-|
+    assert ref["p_plus"] > 10 * w["source"]["p_surface"] and ref["p_plus"] > abs(ref["p_minus"])
+    got = _focal(w, res, prec, zstar=ref["z_index"])
+    c = dg.compare(got, ref)
+    _say(f"  {prec}: p+ {c['p_plus_rel']:.2e} p- {c['p_minus_rel']:.2e} "
+         f"harmonics {['%.1e' % h for h in c['harmonics_rel']]} front {got['front'] - ref['front']:+.3f} cells")
+    assert c["p_plus_rel"] <= tol_peak and c["p_minus_rel"] <= tol_peak
+    for h, tol in zip(c["harmonics_rel"], tol_h):
+        assert h <= tol
+    assert abs(got["front"] - ref["front"]) <= tol_front
