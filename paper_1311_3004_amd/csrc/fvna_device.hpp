@@ -10,13 +10,13 @@
 // segment one row at a time:
 //   * the x1 sweep of a row is lane-parallel; the left neighbour's cell, the
 //     upwind neighbour's wave and the right neighbour's flux come from
-//     cross-lane permutes (ds_bpermute), so every interface is solved once
+//     whole-wave DPP shifts (no LDS round trip), so every interface is solved once
 //     and shared by the two cells it separates;
 //   * the x2 sweep runs down each lane's column on rolling registers: each
 //     new x1-swept row yields one x2 interface, one limited correction and
 //     one x2-swept row;
 //   * the source step of a row needs the x2-swept rows above and below it
-//     (registers) and the lanes beside it (permutes); its result is the only
+//     (registers) and the lanes beside it (DPP shifts); its result is the only
 //     store.
 // Lanes 3..60 produce the 58 output columns; lanes 0..2 and 61..63 are the
 // halo the x1 stencil (two interfaces each side) and the source (one cell)
@@ -150,57 +150,87 @@ __device__ __forceinline__ double perm(double v, int src) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// Neighbour exchange along the wave with DPP whole-wave shifts (gfx9-family
+// VALU, no LDS round trip): from_lo(v) gives lane l the value of lane l - 1,
+// from_hi(v) the value of lane l + 1.  Lane 0 (from_lo) and lane 63
+// (from_hi) receive 0; both are halo lanes whose results are never used.
+constexpr int DPP_WAVE_SHL1 = 0x130;   // lane l reads lane l + 1
+constexpr int DPP_WAVE_SHR1 = 0x138;   // lane l reads lane l - 1
+template <int CTRL> __device__ __forceinline__ int dpp_(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, true);
+}
+template <int CTRL> __device__ __forceinline__ float shift_(float v)
+{
+    return __int_as_float(dpp_<CTRL>(__float_as_int(v)));
+}
+template <int CTRL> __device__ __forceinline__ double shift_(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = dpp_<CTRL>((int)(b & 0xffffffffll));
+    const int hi = dpp_<CTRL>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <typename T> __device__ __forceinline__ T from_lo(T v) { return shift_<DPP_WAVE_SHR1>(v); }
+template <typename T> __device__ __forceinline__ T from_hi(T v) { return shift_<DPP_WAVE_SHL1>(v); }
+
 template <typename T> struct Cell { T R, M, N; };
 
 // Roe wave structure of one interface in split-local components
 // (density, normal momentum, tangential momentum).
 template <typename T> struct Wave { T s1, s2, s3, a1, a2, a3, r1, r2; };
 
+// Markers a Roe solve hands the CFL maximum instead of a speed when the
+// discriminant D is not a positive finite number: NH (+Inf) when D <= 0 or D
+// is NaN (no real wave speeds: the state left the hyperbolic region), NF (the
+// largest finite value) when D = +Inf (overflow).  A running maximum keeps
+// NH over NF over any speed, which is the priority the controller applies.
+template <typename T> __device__ __forceinline__ T cfl_nh() { return T(__builtin_inf()); }
+template <typename T> __device__ __forceinline__ T cfl_nf() { return sizeof(T) == 8 ? T(1.7976931348623157e308) : T(3.40282347e38f); }
+
 // Roe linearisation (Sec. 3.2).  Zbar is the arithmetic mean of
 // z = (q^1, q^2/q^1, q^3/q^1); eigenvalues of eqs. lambda1-3; eigenvectors
 // r^{1,2} = (1, s, zt (s - 2 zn)/(rho zbar (s - w))), r^3 = (0, 0, 1), where
 // w = zn/rho and s - w = +-c; strengths from sum_p alpha^p r^p = Q_R - Q_L.
 // L and R hold (density perturbation, normal momentum, tangential momentum)
-// and the two velocities.  Returns false if the discriminant is not positive.
+// and the two velocities.
 //
-// cfl receives this interface's max_p |s^p| = c + |w| in a form the CFL
-// reduction can carry exactly: FP64 returns it as is; FP32 returns its excess
-// over 1, (c - 1) + |w| with c - 1 = (D - 1)/(1 + c), which keeps ~1e-7
-// relative precision on the excess (so ~1e-10 on the speed itself).  nonfinite
-// is set when the discriminant is +Inf (the FP32 square root pair would turn
-// it into NaN).
+// Returns this interface's max_p |s^p| = c + |w| in a form the CFL reduction
+// can carry exactly -- FP64 as is; FP32 as its excess over 1, (c - 1) + |w|
+// with c - 1 = (D - 1)/(1 + c), which keeps ~1e-7 relative precision on the
+// excess (so ~1e-10 on the speed itself).  mark receives -Inf when D is a
+// positive finite number and one of the markers above otherwise; the caller
+// folds both into its maximum, so no lane branches on D.
 template <typename T>
-__device__ __forceinline__ bool roe(T RL, T nL, T tL, T vnL, T vtL,
-                                    T RR, T nR, T tR, T vnR, T vtR, T beta, Wave<T>& w,
-                                    T& cfl, bool& nonfinite)
+__device__ __forceinline__ T roe(T RL, T nL, T tL, T vnL, T vtL,
+                                 T RR, T nR, T tR, T vnR, T vtR, T beta, Wave<T>& w, T& mark)
 {
-    const T Rb = T(0.5) * (RL + RR);              // Zbar^1 - 1
-    const T irb = rcp(T(1) + Rb);
-    const T zn = T(0.5) * (vnL + vnR);
-    const T zt = T(0.5) * (vtL + vtR);
-    const T wv = zn * irb;
-    const T D1 = fma_(wv, wv - T(2) * zn, T(2) * (beta - T(1)) * Rb);   // D - 1
+    // Sums of the two sides stand for the means (Zbar^1 - 1 = Sr/2, zn = Sn/2,
+    // zt = St/2); every factor of 2 they introduce cancels exactly.
+    const T Sr = RL + RR;
+    const T Sn = vnL + vnR;
+    const T St = vtL + vtR;
+    const T h = rcp(T(2) + Sr);                   // 1 / (2 Zbar^1)
+    const T wv = Sn * h;                          // w = zn / Zbar^1
+    const T D1 = fma_(wv, wv - Sn, (beta - T(1)) * Sr);   // D - 1
     const T D = T(1) + D1;                        // w^2 - 2 zn^2/Zbar^1 + Phi
-    const bool ok = D > T(0);
     T c, ic;
     sqrt_pair(D, c, ic);
-    if constexpr (sizeof(T) == 8) {
-        cfl = c + abs_(wv);
-    } else {
-        cfl = fma_(D1, rcp(T(1) + c), abs_(wv));
-        nonfinite = nonfinite | !(D < __builtin_inff());
-    }
+    T spd;
+    if constexpr (sizeof(T) == 8) spd = c + abs_(wv);
+    else spd = fma_(D1, rcp(T(1) + c), abs_(wv));
     w.s1 = wv + c;
     w.s2 = wv - c;
     w.s3 = wv;
-    const T k = zt * irb * ic;
-    w.r1 = k * (w.s1 - T(2) * zn);
-    w.r2 = -k * (w.s2 - T(2) * zn);
+    const T k = St * h * ic;                      // zt / (Zbar^1 c)
+    w.r1 = k * (w.s1 - Sn);
+    w.r2 = -k * (w.s2 - Sn);
     const T d1 = RR - RL, d2 = nR - nL, d3 = tR - tL;
     w.a1 = T(0.5) * ic * fma_(-w.s2, d1, d2);
     w.a2 = d1 - w.a1;
     w.a3 = fma_(-w.a2, w.r2, fma_(-w.a1, w.r1, d3));
-    return ok;
+    mark = D > T(0) ? (D < cfl_nh<T>() ? -cfl_nh<T>() : cfl_nf<T>()) : cfl_nh<T>();
+    return spd;
 }
 
 // Value the CFL reduction starts from (no interface counted yet) and the
@@ -211,22 +241,33 @@ template <typename T> __device__ __forceinline__ double cfl_speed(T m)
     if constexpr (sizeof(T) == 8) return m;
     else return 1.0 + (double)m;
 }
-
-// MC limiter (Sec. 3.1): phi = max(0, min((1 + theta)/2, 2, 2 theta)).
-template <typename T>
-__device__ __forceinline__ T mc(T th)
+// Controller flags a reduced CFL value carries.
+template <typename T> __device__ __forceinline__ unsigned cfl_flags(T m)
 {
-    return max_(T(0), min_(min_(T(0.5) * (T(1) + th), T(2)), T(2) * th));
+    if (m == cfl_nh<T>()) return FLAG_NONHYP;
+    if (m >= cfl_nf<T>()) return FLAG_NONFINITE;
+    return 0u;
 }
 
-// Products W^p_a . W^p_b of the waves of two neighbouring interfaces, per
-// family, with W^p = alpha^p (1, s^p, r^p) for p = 1, 2 and W^3 = (0, 0, alpha^3).
+// MC limiter (Sec. 3.1), phi(theta) = max(0, min((1 + theta)/2, 2, 2 theta)),
+// evaluated as psi = phi/2 = max(0, min((1 + theta)/4, 1, theta)).  Halving
+// is exact, and hr_split doubles the factor psi multiplies, so the products
+// round exactly as they would with phi.
 template <typename T>
-__device__ __forceinline__ void wave_dots(const Wave<T>& a, const Wave<T>& b, T d[3])
+__device__ __forceinline__ T mc_half(T th)
+{
+    return max_(T(0), min_(min_(fma_(T(0.25), th, T(0.25)), T(1)), th));
+}
+
+// Products W^p_a . W^p_b of the waves of two neighbouring interfaces for the
+// families p = 1, 2, with W^p = alpha^p (1, s^p, r^p).  Family 3 has
+// W^3 = (0, 0, alpha^3), so its ratio needs only the neighbour's alpha^3
+// (hr_split), which is what the third entry carries.
+template <typename T>
+__device__ __forceinline__ void wave_dots(const Wave<T>& a, const Wave<T>& b, T d[2])
 {
     d[0] = (a.a1 * b.a1) * fma_(a.r1, b.r1, fma_(a.s1, b.s1, T(1)));
     d[1] = (a.a2 * b.a2) * fma_(a.r2, b.r2, fma_(a.s2, b.s2, T(1)));
-    d[2] = a.a3 * b.a3;
 }
 
 // theta = (W_up . W) / (W . W) (Sec. 3.1).  The paper's method needs theta
@@ -242,7 +283,8 @@ __device__ __forceinline__ T theta_of(T dup, T a, T s, T r)
 }
 
 // From the waves of one interface and the products of its waves with those of
-// the interface below (dlo) and above (dhi), form
+// the interface below (dlo) and above (dhi) -- entries 0, 1: W^p products of
+// families 1, 2 (wave_dots); entry 2: alpha^3 of that neighbour -- form
 //   Gm = A^- dQ + F~   (applied to the cell on the low side) and
 //   Gp = A^+ dQ - F~   (applied to the cell on the high side);
 // eqs. fluc:m, fluc:p, limiter, fv-hr.  The upwind interface of family p is
@@ -252,15 +294,15 @@ template <typename T>
 __device__ __forceinline__ void hr_split(const Wave<T>& w, const T dlo[3], const T dhi[3], T dt,
                                          T Gm[3], T Gp[3])
 {
-    const T ph1 = mc(theta_of(w.s1 < T(0) ? dhi[0] : dlo[0], w.a1, w.s1, w.r1));
-    const T ph2 = mc(theta_of(w.s2 < T(0) ? dhi[1] : dlo[1], w.a2, w.s2, w.r2));
-    const T ph3 = mc((w.s3 < T(0) ? dhi[2] : dlo[2]) * rcp(w.a3 * w.a3));
+    const T ps1 = mc_half(theta_of(w.s1 < T(0) ? dhi[0] : dlo[0], w.a1, w.s1, w.r1));
+    const T ps2 = mc_half(theta_of(w.s2 < T(0) ? dhi[1] : dlo[1], w.a2, w.s2, w.r2));
+    // family 3: theta = alpha^3_up alpha^3 / (alpha^3)^2 = alpha^3_up / alpha^3
+    const T ps3 = mc_half((w.s3 < T(0) ? dhi[2] : dlo[2]) * rcp(w.a3));
     const T as1 = abs_(w.s1), as2 = abs_(w.s2), as3 = abs_(w.s3);
-    // correction strengths c_p = 1/2 |s| (1 - dt |s|) phi alpha
-    const T hdt = T(0.5) * dt;
-    const T c1 = (fma_(-hdt, as1, T(0.5)) * as1) * (ph1 * w.a1);
-    const T c2 = (fma_(-hdt, as2, T(0.5)) * as2) * (ph2 * w.a2);
-    const T c3 = (fma_(-hdt, as3, T(0.5)) * as3) * (ph3 * w.a3);
+    // correction strengths c_p = 1/2 |s| (1 - dt |s|) phi alpha = |s| (1 - dt |s|) psi alpha
+    const T c1 = (fma_(-dt, as1, T(1)) * as1) * (ps1 * w.a1);
+    const T c2 = (fma_(-dt, as2, T(1)) * as2) * (ps2 * w.a2);
+    const T c3 = (fma_(-dt, as3, T(1)) * as3) * (ps3 * w.a3);
     // e_p = min(s,0) alpha + c_p ; g_p = max(s,0) alpha - c_p = s alpha - e_p
     const T e1 = fma_(min_(w.s1, T(0)), w.a1, c1);
     const T e2 = fma_(min_(w.s2, T(0)), w.a2, c2);
@@ -332,9 +374,59 @@ __device__ __forceinline__ void source_at(const SimDesc& d, double r, double t, 
 }
 
 // ---------------------------------------------------------------------------
+// Raw buffer access.  The lean path (tiles whose rows are all real rows) reads
+// and writes through one buffer resource per field plane covering exactly the
+// rows the tile touches: the row goes in the scalar offset, the column in the
+// lane's vector offset, so a row costs no vector address arithmetic.  The
+// byte count of a resource stays below 2^31; a lane whose vector offset is
+// OFF_NONE lies outside it whatever the scalar offset, and the hardware range
+// check discards its store.
+// ---------------------------------------------------------------------------
+using Rsrc = __amdgpu_buffer_rsrc_t;
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+constexpr int RAW_BUFFER_DWORD3 = 0x00020000;   // raw (unformatted, stride 0) buffer on gfx9-family parts
+constexpr int OFF_NONE = (int)0x80000000u;
+
+__device__ __forceinline__ Rsrc make_rsrc(const void* base, int bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, bytes, RAW_BUFFER_DWORD3);
+}
+__device__ __forceinline__ void bld(Rsrc r, int vo, int so, double& x)
+{
+    x = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+}
+__device__ __forceinline__ void bld(Rsrc r, int vo, int so, float& x)
+{
+    x = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+}
+__device__ __forceinline__ void bld(Rsrc r, int vo, int so, _Float16& x)
+{
+    x = __builtin_bit_cast(_Float16, (unsigned short)__builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0));
+}
+__device__ __forceinline__ void bld(Rsrc r, int vo, int so, bf16& x)
+{
+    x.bits = (uint16_t)__builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0);
+}
+__device__ __forceinline__ void bst(Rsrc r, int vo, int so, double x)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), r, vo, so, 0);
+}
+__device__ __forceinline__ void bst(Rsrc r, int vo, int so, float x)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), r, vo, so, 0);
+}
+__device__ __forceinline__ void bst(Rsrc r, int vo, int so, _Float16 x)
+{
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, x), r, vo, so, 0);
+}
+__device__ __forceinline__ void bst(Rsrc r, int vo, int so, bf16 x)
+{
+    __builtin_amdgcn_raw_buffer_store_b16(x.bits, r, vo, so, 0);
+}
+
+// ---------------------------------------------------------------------------
 // The fused step of one wavefront tile.
 // ---------------------------------------------------------------------------
-
 
 // State one lane carries from one x2 row to the next.  Every entry is
 // consumed by the very next row, so two copies alternated by a two-row
@@ -342,7 +434,7 @@ __device__ __forceinline__ void source_at(const SimDesc& d, double r, double t, 
 template <typename T> struct Carry {
     Cell<T> q; T u, v;      // last x1-swept row Q*_v pushed, and its velocities
     Wave<T> w;              // x2 interface v - 1/2
-    T dlo[3];               // W_{v-3/2} . W_{v-1/2} per family
+    T dlo[3];               // W_{v-3/2} . W_{v-1/2} (families 1, 2) and alpha^3_{v-3/2}
     Cell<T> part;           // Q*_{v-1} - dt Gp_{v-3/2}: row v-1 awaiting its upper flux
     Cell<T> qs; T us, vs;   // x2-swept row v-2 awaiting its source, and its velocities
     T ub, vb;               // velocities of x2-swept row v-3
@@ -360,11 +452,18 @@ __device__ __forceinline__ void carry_zero(Carry<T>& c)
     c.ub = z; c.vb = z;
 }
 
-// One wavefront tile of the fused step.  EDGE: the strip touches a
-// non-periodic x side (ghost columns and x overrides needed); interior strips
-// compile without any of that logic.
-template <typename S, typename T, int AXI, bool EDGE>
-__device__ __forceinline__ void march(const SimDesc& d, int strip, int seg, bool count)
+template <bool B> struct Flag { static constexpr bool value = B; };
+
+// One wavefront tile of the fused step.
+//   EDGE: the strip touches a non-periodic x side (ghost columns and x
+//         overrides needed); interior strips compile without that logic.
+//   LEAN: every row the tile touches (three below the segment to three above)
+//         is a real row: no ghost rows, no periodic wrap, no boundary rows in
+//         the source, and the main loop has no branches at all.  Other
+//         segments take the general path.  Both paths evaluate every cell
+//         with the same arithmetic, so results do not depend on the path.
+template <typename S, typename T, int AXI, bool EDGE, bool LEAN>
+__device__ __forceinline__ void march(const SimDesc& d, int strip, int seg)
 {
     using C = Codec<S, T>;
     const int lane = threadIdx.x & (WAVE - 1);
@@ -420,22 +519,41 @@ __device__ __forceinline__ void march(const SimDesc& d, int strip, int seg, bool
         scol = min(max(scol, 0), nx - 1);
     }
     const bool real_col = perx || incol;
-    const bool cnt_x = count && lane >= 1 && (perx || (col >= 0 && col <= nx));
-    const bool cnt_y = count && lane >= 2 && lane <= WAVE - 3 && real_col;
     const bool out_lane = lane >= HALO && lane < WAVE - HALO && col < nx;
-    const int lm1 = lane - 1, lp1 = lane + 1;
     const bool ghost_lo = EDGE && !perx && col == 0;        // left neighbour of this output cell is a ghost
     const bool ghost_hi = EDGE && !perx && col == nx - 1;   // right neighbour is a ghost
 
-    T smax = cfl_floor<T>();
-    bool bad = false, nonfin = false;
+    // Per-lane running maxima of the CFL entries, x1 and x2 interfaces
+    // apart; which lanes hold real interfaces is applied once at the end (a
+    // maximum is indifferent to order and repetition).
+    T xmax = cfl_floor<T>(), ymax = cfl_floor<T>();
+
+    // ---- lean path: buffer resources over rows rs .. vlast ----
+    const int rs = r0 - HALO;
+    const int vlast = r1 + HALO - 1;
+    const int pb = d.pitch * (int)sizeof(S);
+    const int tile_bytes = (vlast - rs + 1) * pb;
+    const size_t rso = (size_t)(LEAN ? rs : 0) * pitch;
+    const Rsrc iR = make_rsrc(inR + rso, tile_bytes), iM = make_rsrc(inM + rso, tile_bytes),
+               iN = make_rsrc(inN + rso, tile_bytes);
+    const Rsrc oR = make_rsrc(outR + rso, tile_bytes), oM = make_rsrc(outM + rso, tile_bytes),
+               oN = make_rsrc(outN + rso, tile_bytes);
+    const int vld = scol * (int)sizeof(S);
+    const int vst = out_lane ? col * (int)sizeof(S) : OFF_NONE;
 
     // ---- raw loads of one row of Q^n (real row index) ----
     auto load_row = [&](int vr, S& a, S& b, S& c) {
-        const size_t o = (size_t)vr * pitch + (size_t)scol;
-        a = inR[o];
-        b = inM[o];
-        c = inN[o];
+        if constexpr (LEAN) {
+            const int so = (min(vr, vlast) - rs) * pb;     // rows past the tile: harmless repeat
+            bld(iR, vld, so, a);
+            bld(iM, vld, so, b);
+            bld(iN, vld, so, c);
+        } else {
+            const size_t o = (size_t)vr * pitch + (size_t)scol;
+            a = inR[o];
+            b = inM[o];
+            c = inN[o];
+        }
     };
 
     // ---- x1 sweep of one row (lane-parallel) ----
@@ -457,29 +575,25 @@ __device__ __forceinline__ void march(const SimDesc& d, int strip, int seg, bool
         }
         const T irho = rcp(T(1) + q.R);
         const T u = q.M * irho, v = q.N * irho;
-        const T RL = perm(q.R, lm1), ML = perm(q.M, lm1), NL = perm(q.N, lm1);
-        const T uL = perm(u, lm1), vL = perm(v, lm1);
+        const T RL = from_lo(q.R), ML = from_lo(q.M), NL = from_lo(q.N);
+        const T uL = from_lo(u), vL = from_lo(v);
         Wave<T> w;
-        T cfl;
-        bool nf = false;
-        const bool ok = roe(RL, ML, NL, uL, vL, q.R, q.M, q.N, u, v, beta, w, cfl, nf);
-        if (cnt_x) {
-            bad |= !ok;
-            nonfin |= nf;
-            smax = max_(smax, cfl);
-        }
+        T mark;
+        const T spd = roe(RL, ML, NL, uL, vL, q.R, q.M, q.N, u, v, beta, w, mark);
+        xmax = max_(max_(xmax, spd), mark);
         // waves of the interface to the right -> products with it; the lane
         // to the left supplies the products with the interface below
         Wave<T> wr;
-        wr.a1 = perm(w.a1, lp1); wr.s1 = perm(w.s1, lp1); wr.r1 = perm(w.r1, lp1);
-        wr.a2 = perm(w.a2, lp1); wr.s2 = perm(w.s2, lp1); wr.r2 = perm(w.r2, lp1);
-        wr.a3 = perm(w.a3, lp1);
+        wr.a1 = from_hi(w.a1); wr.s1 = from_hi(w.s1); wr.r1 = from_hi(w.r1);
+        wr.a2 = from_hi(w.a2); wr.s2 = from_hi(w.s2); wr.r2 = from_hi(w.r2);
+        wr.a3 = from_hi(w.a3);
         T dhi[3], dlo[3];
         wave_dots(w, wr, dhi);
-        dlo[0] = perm(dhi[0], lm1); dlo[1] = perm(dhi[1], lm1); dlo[2] = perm(dhi[2], lm1);
+        dhi[2] = wr.a3;
+        dlo[0] = from_lo(dhi[0]); dlo[1] = from_lo(dhi[1]); dlo[2] = from_lo(w.a3);
         T Gm[3], Gp[3];
         hr_split(w, dlo, dhi, dt, Gm, Gp);
-        const T g0 = perm(Gm[0], lp1), g1 = perm(Gm[1], lp1), g2 = perm(Gm[2], lp1);
+        const T g0 = from_hi(Gm[0]), g1 = from_hi(Gm[1]), g2 = from_hi(Gm[2]);
         Cell<T> o2;
         o2.R = fma_(-dt, g0 + Gp[0], q.R);
         o2.M = fma_(-dt, g1 + Gp[1], q.M);
@@ -496,24 +610,21 @@ __device__ __forceinline__ void march(const SimDesc& d, int strip, int seg, bool
         vv = (T)(N / (1.0 + R));
     };
 
-    const int vfirst = r0 - HALO;
+    const int vfirst = rs;
 
     // ---- push x1-swept row v through the x2 sweep and the source ----
-    auto push = [&](const Cell<T>& q, int v, const Carry<T>& in, Carry<T>& out) {
+    // src (lean path): whether row v - 3 is an output row of this tile.
+    auto push = [&](const Cell<T>& q, int v, const Carry<T>& in, Carry<T>& out, auto src) {
         const T irho = rcp(T(1) + q.R);
         const T u = q.M * irho, vv = q.N * irho;
         // x2 interface v-1/2 between rows v-1 (low) and v (high); normal = N
         Wave<T> wA;
-        T cfl;
-        bool nf = false;
-        const bool ok = roe(in.q.R, in.q.N, in.q.M, in.v, in.u, q.R, q.N, q.M, vv, u, beta, wA, cfl, nf);
-        if (cnt_y && v > vfirst && (pery || (v >= 0 && v <= ny))) {
-            bad |= !ok;
-            nonfin |= nf;
-            smax = max_(smax, cfl);
-        }
+        T mark;
+        const T spd = roe(in.q.R, in.q.N, in.q.M, in.v, in.u, q.R, q.N, q.M, vv, u, beta, wA, mark);
+        if (LEAN || (v > vfirst && (pery || (v >= 0 && v <= ny)))) ymax = max_(max_(ymax, spd), mark);
         T dhi[3];
         wave_dots(in.w, wA, dhi);
+        dhi[2] = wA.a3;
         // limited correction and fluctuations at v-3/2
         T Gm[3], Gp[3];
         hr_split(in.w, in.dlo, dhi, dt, Gm, Gp);
@@ -530,9 +641,12 @@ __device__ __forceinline__ void march(const SimDesc& d, int strip, int seg, bool
         const T un = qn.M * irn, vn = qn.N * irn;
         // source of row j = v-3 (x2-swept rows j-1, j, j+1), then store
         const int j = v - 3;
-        if (j >= r0 && j < r1) {
-            T uxl = perm(in.us, lm1), vxl = perm(in.vs, lm1);
-            T uxr = perm(in.us, lp1), vxr = perm(in.vs, lp1);
+        bool do_src;
+        if constexpr (LEAN) do_src = decltype(src)::value;
+        else do_src = j >= r0 && j < r1;
+        if (do_src) {
+            T uxl = from_lo(in.us), vxl = from_lo(in.vs);
+            T uxr = from_hi(in.us), vxr = from_hi(in.vs);
             T ubl = in.ub, vbl = in.vb, uab = un, vab = vn;
             if (EDGE) {
                 if (ghost_lo) {
@@ -553,149 +667,197 @@ __device__ __forceinline__ void march(const SimDesc& d, int strip, int seg, bool
                     else { uxr = in.us; vxr = in.vs; }
                 }
             }
-            if (!pery && j == 0) {
-                const int b = d.bc[2];
-                if (b == BC_REFLECT) { ubl = in.us; vbl = -in.vs; }
-                else if (b == BC_TAYLOR) taylor_uv(col + 0.5, -0.5, ubl, vbl);
-                else { ubl = in.us; vbl = in.vs; }
+            if constexpr (!LEAN) {
+                if (!pery && j == 0) {
+                    const int b = d.bc[2];
+                    if (b == BC_REFLECT) { ubl = in.us; vbl = -in.vs; }
+                    else if (b == BC_TAYLOR) taylor_uv(col + 0.5, -0.5, ubl, vbl);
+                    else { ubl = in.us; vbl = in.vs; }
+                }
+                if (!pery && j == ny - 1) {
+                    const int b = d.bc[3];
+                    if (b == BC_REFLECT) { uab = in.us; vab = -in.vs; }
+                    else if (b == BC_TAYLOR) taylor_uv(col + 0.5, ny + 0.5, uab, vab);
+                    else { uab = in.us; vab = in.vs; }
+                }
             }
-            if (!pery && j == ny - 1) {
-                const int b = d.bc[3];
-                if (b == BC_REFLECT) { uab = in.us; vab = -in.vs; }
-                else if (b == BC_TAYLOR) taylor_uv(col + 0.5, ny + 0.5, uab, vab);
-                else { uab = in.us; vab = in.vs; }
-            }
-            const T lapu = ((uxl + uxr) + (ubl + uab)) - T(4) * in.us;
-            const T lapv = ((vxl + vxr) + (vbl + vab)) - T(4) * in.vs;
-            const T oR = in.qs.R;
-            T oM, oN;
+            const T lapu = fma_(T(-4), in.us, (uxl + uxr) + (ubl + uab));
+            const T lapv = fma_(T(-4), in.vs, (vxl + vxr) + (vbl + vab));
+            const T oRv = in.qs.R;
+            T oMv, oNv;
             if constexpr (AXI) {
                 // cylindrical vector Laplacian: + (1/r) d/dr of each velocity, - v/r^2
                 const T ir = rcp(T(j) + T(0.5));
                 const T dur = T(0.5) * (uab - ubl), dvr = T(0.5) * (vab - vbl);
                 const T k = dt * delta;
-                oM = fma_(k, fma_(dur, ir, lapu), in.qs.M);
-                oN = fma_(k, fma_(-in.vs, ir * ir, fma_(dvr, ir, lapv)), in.qs.N);
+                oMv = fma_(k, fma_(dur, ir, lapu), in.qs.M);
+                oNv = fma_(k, fma_(-in.vs, ir * ir, fma_(dvr, ir, lapv)), in.qs.N);
             } else {
                 const T k = dt * delta;
-                oM = fma_(k, lapu, in.qs.M);
-                oN = fma_(k, lapv, in.qs.N);
+                oMv = fma_(k, lapu, in.qs.M);
+                oNv = fma_(k, lapv, in.qs.N);
             }
-            if (out_lane) {
+            if constexpr (LEAN) {
+                const int so = (j - rs) * pb;
+                bst(oR, vst, so, C::st(oRv, is0));
+                bst(oM, vst, so, C::st(oMv, is1));
+                bst(oN, vst, so, C::st(oNv, is2));
+            } else if (out_lane) {
                 const size_t o = (size_t)j * pitch + (size_t)col;
-                outR[o] = C::st(oR, is0);
-                outM[o] = C::st(oM, is1);
-                outN[o] = C::st(oN, is2);
+                outR[o] = C::st(oRv, is0);
+                outM[o] = C::st(oMv, is1);
+                outN[o] = C::st(oNv, is2);
             }
         }
         out.q = q; out.u = u; out.v = vv;
         out.w = wA;
-        out.dlo[0] = dhi[0]; out.dlo[1] = dhi[1]; out.dlo[2] = dhi[2];
+        out.dlo[0] = dhi[0]; out.dlo[1] = dhi[1]; out.dlo[2] = in.w.a3;
         out.qs = qn; out.us = un; out.vs = vn;
         out.ub = in.us; out.vb = in.vs;
     };
 
     Carry<T> A, B;
     carry_zero(A);
-    carry_zero(B);
-    Cell<T> stash = {T(0), T(0), T(0)};    // x1-swept row ny-2 (reflecting top ghost)
-    auto keep = [&](const Cell<T>& q, int v) { if (v == ny - 2) stash = q; };
 
-    int v = vfirst;
-    if (!pery && r0 == 0) {
-        // bottom side: the ghost rows of the x1-swept state need rows 0 and 1 first
-        S a0, b0, c0_, a1, b1, c1;
-        load_row(0, a0, b0, c0_);
-        load_row(1, a1, b1, c1);
-        const Cell<T> q0 = xsweep(0, a0, b0, c0_);
-        const Cell<T> q1 = xsweep(1, a1, b1, c1);
-        const int b = d.bc[2];
-        Cell<T> g[HALO];
-        for (int k = HALO; k >= 1; --k) {       // rows -3, -2, -1
-            Cell<T> q;
+    if constexpr (LEAN) {
+        // two rows of Q^n in flight ahead of the one being swept
+        S a0, b0, e0, a1, b1, e1;
+        load_row(rs, a0, b0, e0);
+        load_row(rs + 1, a1, b1, e1);
+        int v = rs;
+        // six warm-up rows, no source; the lowest x2 interface borders the
+        // zeroed carry and is dropped from the CFL maximum
+#pragma unroll 1
+        for (int k = 0; k < 3; ++k, v += 2) {
+            S a = a0, b = b0, e = e0;
+            load_row(v + 2, a0, b0, e0);
+            push(xsweep(v, a, b, e), v, A, B, Flag<false>{});
+            if (k == 0) ymax = cfl_floor<T>();
+            a = a1; b = b1; e = e1;
+            load_row(v + 3, a1, b1, e1);
+            push(xsweep(v + 1, a, b, e), v + 1, B, A, Flag<false>{});
+        }
+        // output rows r0 .. r1-1 (pushed rows r0+3 .. r1+2)
+#pragma unroll 1
+        for (; v + 1 <= vlast; v += 2) {
+            S a = a0, b = b0, e = e0;
+            load_row(v + 2, a0, b0, e0);
+            push(xsweep(v, a, b, e), v, A, B, Flag<true>{});
+            a = a1; b = b1; e = e1;
+            load_row(v + 3, a1, b1, e1);
+            push(xsweep(v + 1, a, b, e), v + 1, B, A, Flag<true>{});
+        }
+        if (v <= vlast) push(xsweep(v, a0, b0, e0), v, A, B, Flag<true>{});
+    } else {
+        carry_zero(B);
+        Cell<T> stash = {T(0), T(0), T(0)};    // x1-swept row ny-2 (reflecting top ghost)
+        auto keep = [&](const Cell<T>& q, int v) { if (v == ny - 2) stash = q; };
+        const Flag<true> any;
+
+        int v = vfirst;
+        if (!pery && r0 == 0) {
+            // bottom side: the ghost rows of the x1-swept state need rows 0 and 1 first
+            S a0, b0, c0_, a1, b1, c1;
+            load_row(0, a0, b0, c0_);
+            load_row(1, a1, b1, c1);
+            const Cell<T> q0 = xsweep(0, a0, b0, c0_);
+            const Cell<T> q1 = xsweep(1, a1, b1, c1);
+            const int b = d.bc[2];
+            Cell<T> g[HALO];
+            for (int k = HALO; k >= 1; --k) {       // rows -3, -2, -1
+                Cell<T> q;
+                if (b == BC_TAYLOR) {
+                    double R, M, N;
+                    taylor_at(d, col + 0.5, -k + 0.5, tn, R, M, N);
+                    q.R = (T)R; q.M = (T)M; q.N = (T)N;
+                } else if (b == BC_REFLECT) {
+                    q = (k == 1) ? q0 : q1;
+                    q.N = -q.N;
+                } else {
+                    q = q0;
+                }
+                g[k - 1] = q;
+            }
+            push(g[2], -3, A, B, any);
+            push(g[1], -2, B, A, any);
+            push(g[0], -1, A, B, any);
+            push(q0, 0, B, A, any); keep(q0, 0);
+            push(q1, 1, A, B, any); keep(q1, 1);
+            A = B;
+            v = 2;
+        }
+        // real rows, two per iteration, loads one row ahead
+        const int vreal = pery ? vlast : min(vlast, ny - 1);
+        auto wrap = [&](int vv) { return pery ? ((vv % ny) + ny) % ny : vv; };
+        if (v <= vreal) {
+            S na, nb, nc;
+            load_row(wrap(v), na, nb, nc);
+            for (; v + 1 <= vreal; v += 2) {
+                S a = na, b = nb, c = nc;
+                load_row(wrap(v + 1), na, nb, nc);
+                const Cell<T> q = xsweep(wrap(v), a, b, c);
+                push(q, v, A, B, any); keep(q, v);
+                a = na; b = nb; c = nc;
+                if (v + 2 <= vreal) load_row(wrap(v + 2), na, nb, nc);
+                const Cell<T> q2 = xsweep(wrap(v + 1), a, b, c);
+                push(q2, v + 1, B, A, any); keep(q2, v + 1);
+            }
+            if (v <= vreal) {
+                const Cell<T> q = xsweep(wrap(v), na, nb, nc);
+                push(q, v, A, B, any); keep(q, v);
+                A = B;
+                ++v;
+            }
+        }
+        // ghost rows above a non-periodic top side
+        for (; v <= vlast; ++v) {
+            const int b = d.bc[3];
+            Cell<T> q = A.q;                           // zero-order extrapolation of Q*_{ny-1}
             if (b == BC_TAYLOR) {
                 double R, M, N;
-                taylor_at(d, col + 0.5, -k + 0.5, tn, R, M, N);
+                taylor_at(d, col + 0.5, v + 0.5, tn, R, M, N);
                 q.R = (T)R; q.M = (T)M; q.N = (T)N;
             } else if (b == BC_REFLECT) {
-                q = (k == 1) ? q0 : q1;
-                q.N = -q.N;
-            } else {
-                q = q0;
+                if (v == ny) { q = A.q; q.N = -q.N; }
+                else if (v == ny + 1) { q = stash; q.N = -q.N; }
             }
-            g[k - 1] = q;
-        }
-        push(g[2], -3, A, B);
-        push(g[1], -2, B, A);
-        push(g[0], -1, A, B);
-        push(q0, 0, B, A); keep(q0, 0);
-        push(q1, 1, A, B); keep(q1, 1);
-        A = B;
-        v = 2;
-    }
-    // real rows, two per iteration, loads one row ahead
-    const int vlast = r1 + HALO - 1;
-    const int vreal = pery ? vlast : min(vlast, ny - 1);
-    auto wrap = [&](int vv) { return pery ? ((vv % ny) + ny) % ny : vv; };
-    if (v <= vreal) {
-        S na, nb, nc;
-        load_row(wrap(v), na, nb, nc);
-        for (; v + 1 <= vreal; v += 2) {
-            S a = na, b = nb, c = nc;
-            load_row(wrap(v + 1), na, nb, nc);
-            const Cell<T> q = xsweep(wrap(v), a, b, c);
-            push(q, v, A, B); keep(q, v);
-            a = na; b = nb; c = nc;
-            if (v + 2 <= vreal) load_row(wrap(v + 2), na, nb, nc);
-            const Cell<T> q2 = xsweep(wrap(v + 1), a, b, c);
-            push(q2, v + 1, B, A); keep(q2, v + 1);
-        }
-        if (v <= vreal) {
-            const Cell<T> q = xsweep(wrap(v), na, nb, nc);
-            push(q, v, A, B); keep(q, v);
+            push(q, v, A, B, any);
             A = B;
-            ++v;
         }
-    }
-    // ghost rows above a non-periodic top side
-    for (; v <= vlast; ++v) {
-        const int b = d.bc[3];
-        Cell<T> q = A.q;                           // zero-order extrapolation of Q*_{ny-1}
-        if (b == BC_TAYLOR) {
-            double R, M, N;
-            taylor_at(d, col + 0.5, v + 0.5, tn, R, M, N);
-            q.R = (T)R; q.M = (T)M; q.N = (T)N;
-        } else if (b == BC_REFLECT) {
-            if (v == ny) { q = A.q; q.N = -q.N; }
-            else if (v == ny + 1) { q = stash; q.N = -q.N; }
-        }
-        push(q, v, A, B);
-        A = B;
     }
 
-    // ---- wave reductions: max |s| and the non-hyperbolic flag ----
-    if (count) {
-        T m = smax;
-        for (int off = 32; off >= 1; off >>= 1) m = max_(m, perm(m, lane ^ off));
-        const bool anybad = __any(bad);
-        const bool anynf = __any(nonfin);
-        if (lane == 0) {
-            const double md = cfl_speed<T>(m);
-            atomicMax(&d.clk->smax_bits, (unsigned long long)__double_as_longlong(md));
-            const unsigned fl = (anybad ? FLAG_NONHYP : 0u) | (anynf ? FLAG_NONFINITE : 0u);
-            if (fl) atomicOr(&d.clk->flags, fl);
-        }
+    // ---- wave reduction of the CFL entries over real interfaces ----
+    // x1 interface of lane l: between columns col-1 and col (lane 0 has no
+    // left neighbour); x2 interfaces: lanes whose x1-swept values are exact.
+    const bool cnt_x = lane >= 1 && (perx || (col >= 0 && col <= nx));
+    const bool cnt_y = lane >= 2 && lane <= WAVE - 3 && real_col;
+    T m = max_(cnt_x ? xmax : cfl_floor<T>(), cnt_y ? ymax : cfl_floor<T>());
+    for (int off = 32; off >= 1; off >>= 1) m = max_(m, perm(m, lane ^ off));
+    if (lane == 0) {
+        atomicMax(&d.clk->smax_bits, (unsigned long long)__double_as_longlong(cfl_speed<T>(m)));
+        const unsigned fl = cfl_flags<T>(m);
+        if (fl) atomicOr(&d.clk->flags, fl);
     }
 }
 
-// Interior strips (no ghost column, no x override) take the lean variant.
+// Interior strips (no ghost column, no x override) take the EDGE = false
+// variant; segments whose rows are all real rows take the lean path.
 template <typename S, typename T, int AXI>
-__device__ __forceinline__ void march_tile(const SimDesc& d, int strip, int seg, bool count)
+__device__ __forceinline__ void march_tile(const SimDesc& d, int strip, int seg)
 {
     const int c0 = strip * OUTW;
     const bool interior = d.bc[0] == BC_PERIODIC || (c0 - HALO >= 0 && c0 + OUTW + HALO - 1 <= d.nx - 1);
-    if (interior) march<S, T, AXI, false>(d, strip, seg, count);
-    else march<S, T, AXI, true>(d, strip, seg, count);
+    const int r0 = seg * d.tile_rows;
+    const int r1 = min(r0 + d.tile_rows, d.ny);
+    const bool lean = r0 >= HALO && r1 + HALO <= d.ny &&
+                      (long long)(r1 - r0 + 2 * HALO) * d.pitch * (long long)sizeof(S) < (1ll << 31);
+    if (interior) {
+        if (lean) march<S, T, AXI, false, true>(d, strip, seg);
+        else march<S, T, AXI, false, false>(d, strip, seg);
+    } else {
+        if (lean) march<S, T, AXI, true, true>(d, strip, seg);
+        else march<S, T, AXI, true, false>(d, strip, seg);
+    }
 }
 
 }  // namespace fvna

@@ -77,7 +77,10 @@ __global__ void k_ctrl_batch(const SimDesc* __restrict__ descs, int n)
 
 // Waves per SIMD the register allocation must allow: four for FP32 compute
 // (measured faster than three with a few more registers), two for FP64.
-template <typename T> struct Occupancy { static constexpr int waves = sizeof(T) == 8 ? 2 : 4; };
+#ifndef FVNA_F32_WAVES_PER_SIMD
+#define FVNA_F32_WAVES_PER_SIMD 4
+#endif
+template <typename T> struct Occupancy { static constexpr int waves = sizeof(T) == 8 ? 2 : FVNA_F32_WAVES_PER_SIMD; };
 
 // One attempted step over the whole grid.  force = 1 (timing): run even when
 // no step is owed.
@@ -90,7 +93,7 @@ void k_step(SimDesc d, int force)
     if (tile >= d.strips * d.segs) return;
     const Clock* clk = d.clk;
     if (!force && (clk->status != 0 || clk->accepted >= clk->target)) return;
-    march_tile<S, T, AXI>(d, tile % d.strips, tile / d.strips, true);
+    march_tile<S, T, AXI>(d, tile % d.strips, tile / d.strips);
 }
 
 struct TileRef { int sim, strip, seg, pad; };
@@ -106,7 +109,7 @@ void k_step_batch(const SimDesc* __restrict__ descs, const TileRef* __restrict__
     const SimDesc& d = descs[tr.sim];
     const Clock* clk = d.clk;
     if (!force && (clk->status != 0 || clk->accepted >= clk->target)) return;
-    march_tile<S, T, AXI>(d, tr.strip, tr.seg, true);
+    march_tile<S, T, AXI>(d, tr.strip, tr.seg);
 }
 
 __global__ void k_bump(Clock* c, long long n)
@@ -180,31 +183,29 @@ __global__ __launch_bounds__(256) void k_dry(SimDesc d)
     const double t = d.clk->t;
     const T beta = (T)d.beta;
     T sm = cfl_floor<T>();
-    bool bad = false, nf = false;
     if (i <= d.nx) {
-        T cfl;
         if (j < d.ny) {
             const Cell<T> a = cell_at<S, T>(d, i - 1, j, t), b = cell_at<S, T>(d, i, j, t);
             const T ia = rcp(T(1) + a.R), ib = rcp(T(1) + b.R);
             Wave<T> w;
-            bad |= !roe(a.R, a.M, a.N, a.M * ia, a.N * ia, b.R, b.M, b.N, b.M * ib, b.N * ib, beta, w, cfl, nf);
-            sm = max_(sm, cfl);
+            T mark;
+            const T spd = roe(a.R, a.M, a.N, a.M * ia, a.N * ia, b.R, b.M, b.N, b.M * ib, b.N * ib, beta, w, mark);
+            sm = max_(max_(sm, spd), mark);
         }
         if (i < d.nx) {
             const Cell<T> a = cell_at<S, T>(d, i, j - 1, t), b = cell_at<S, T>(d, i, j, t);
             const T ia = rcp(T(1) + a.R), ib = rcp(T(1) + b.R);
             Wave<T> w;
-            bad |= !roe(a.R, a.N, a.M, a.N * ia, a.M * ia, b.R, b.N, b.M, b.N * ib, b.M * ib, beta, w, cfl, nf);
-            sm = max_(sm, cfl);
+            T mark;
+            const T spd = roe(a.R, a.N, a.M, a.N * ia, a.M * ia, b.R, b.N, b.M, b.N * ib, b.M * ib, beta, w, mark);
+            sm = max_(max_(sm, spd), mark);
         }
     }
     const int lane = threadIdx.x & 63;
     for (int off = 32; off >= 1; off >>= 1) sm = max_(sm, perm(sm, lane ^ off));
-    const bool anybad = __any(bad);
-    const bool anynf = __any(nf);
     if (lane == 0) {
         atomicMax(&d.clk->smax_bits, (unsigned long long)__double_as_longlong(cfl_speed<T>(sm)));
-        const unsigned fl = (anybad ? FLAG_NONHYP : 0u) | (anynf ? FLAG_NONFINITE : 0u);
+        const unsigned fl = cfl_flags<T>(sm);
         if (fl) atomicOr(&d.clk->flags, fl);
     }
 }
@@ -399,7 +400,7 @@ size_t scratch_bytes_of(const fvna_params* p)
 // warm-up rows of a segment are redundant work).
 int default_tile_rows(const fvna_params* p, int cu_count)
 {
-    const int waves_per_simd = p->precision == FVNA_F64 ? 2 : 4;
+    const int waves_per_simd = p->precision == FVNA_F64 ? Occupancy<double>::waves : Occupancy<float>::waves;
     const long long slots = (long long)std::max(cu_count, 1) * 4 * waves_per_simd;
     const long long strips = (p->nx + OUTW - 1) / OUTW;
     const long long per_strip = std::max(1ll, slots / strips);
