@@ -454,6 +454,33 @@ __device__ __forceinline__ void carry_zero(Carry<T>& c)
 
 template <bool B> struct Flag { static constexpr bool value = B; };
 
+// Issue priority from progress.  Among waves of equal priority the SIMD
+// arbiter favours the oldest, so the waves that start together on a SIMD
+// would finish one after another and leave it with one or two waves (and a
+// fraction of its issue rate) for the last part of the step.  A wave lowers
+// its priority as it advances -- 3 for the first half of its rows, 2 to three
+// quarters, 1 to nine tenths, 0 after -- so the waves of a SIMD stay level and
+// keep it full until they all finish.  Priority changes timing only.
+struct Pace {
+    int b1, b2, b3;          // row counts at which the priority drops
+    int level;
+    __device__ __forceinline__ explicit Pace(int total)
+        : b1(total / 2), b2((3 * total) / 4), b3((9 * total) / 10), level(3)
+    {
+        __builtin_amdgcn_s_setprio(3);
+    }
+    __device__ __forceinline__ void update(int done)
+    {
+        const int want = done < b1 ? 3 : done < b2 ? 2 : done < b3 ? 1 : 0;
+        if (want != level) {
+            level = want;
+            if (want == 2) __builtin_amdgcn_s_setprio(2);
+            else if (want == 1) __builtin_amdgcn_s_setprio(1);
+            else __builtin_amdgcn_s_setprio(0);
+        }
+    }
+};
+
 // One wavefront tile of the fused step.
 //   EDGE: the strip touches a non-periodic x side (ghost columns and x
 //         overrides needed); interior strips compile without that logic.
@@ -738,8 +765,10 @@ __device__ __forceinline__ void march(const SimDesc& d, int strip, int seg)
             push(xsweep(v + 1, a, b, e), v + 1, B, A, Flag<false>{});
         }
         // output rows r0 .. r1-1 (pushed rows r0+3 .. r1+2)
+        Pace pace(vlast - rs + 1);
 #pragma unroll 1
         for (; v + 1 <= vlast; v += 2) {
+            pace.update(v - rs);
             S a = a0, b = b0, e = e0;
             load_row(v + 2, a0, b0, e0);
             push(xsweep(v, a, b, e), v, A, B, Flag<true>{});
@@ -792,7 +821,9 @@ __device__ __forceinline__ void march(const SimDesc& d, int strip, int seg)
         if (v <= vreal) {
             S na, nb, nc;
             load_row(wrap(v), na, nb, nc);
+            Pace pace(vlast - vfirst + 1);
             for (; v + 1 <= vreal; v += 2) {
+                pace.update(v - vfirst);
                 S a = na, b = nb, c = nc;
                 load_row(wrap(v + 1), na, nb, nc);
                 const Cell<T> q = xsweep(wrap(v), a, b, c);

@@ -75,10 +75,12 @@ __global__ void k_ctrl_batch(const SimDesc* __restrict__ descs, int n)
     if (k < n) control(descs[k]);
 }
 
-// Waves per SIMD the register allocation must allow: four for FP32 compute
-// (measured faster than three with a few more registers), two for FP64.
+// Waves per SIMD the register allocation must allow: three for FP32 compute
+// (168 VGPRs, no spills; with tiles that fill every slot in one round this
+// measured 9% faster than four waves at 128 VGPRs on a 4096^2 grid and level
+// on 8192^2), two for FP64.
 #ifndef FVNA_F32_WAVES_PER_SIMD
-#define FVNA_F32_WAVES_PER_SIMD 4
+#define FVNA_F32_WAVES_PER_SIMD 3
 #endif
 template <typename T> struct Occupancy { static constexpr int waves = sizeof(T) == 8 ? 2 : FVNA_F32_WAVES_PER_SIMD; };
 
