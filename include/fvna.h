@@ -53,8 +53,8 @@ typedef enum {
     FVNA_E_INVALID = 1,        /* bad argument; nothing changed */
     FVNA_E_NOMEM = 2,          /* host allocation failed */
     FVNA_E_HIP = 3,            /* a HIP runtime call failed (message has the HIP error) */
-    FVNA_E_NONHYPERBOLIC = 4,  /* Roe discriminant <= 0 (eigenvalues not real, Sec. 3.2) */
-    FVNA_E_NONFINITE = 5,      /* largest wave speed of a step is Inf or NaN */
+    FVNA_E_NONHYPERBOLIC = 4,  /* Roe discriminant <= 0 or NaN (eigenvalues not real, Sec. 3.2) */
+    FVNA_E_NONFINITE = 5,      /* otherwise: a discriminant or the largest wave speed is +Inf or NaN */
     FVNA_E_RETRIES = 6,        /* more than max_retries rejected attempts in a row */
     FVNA_E_STATE = 7           /* call not valid in the current state */
 } fvna_status;

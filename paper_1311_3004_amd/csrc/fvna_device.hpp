@@ -180,14 +180,6 @@ template <typename T> struct Cell { T R, M, N; };
 // (density, normal momentum, tangential momentum).
 template <typename T> struct Wave { T s1, s2, s3, a1, a2, a3, r1, r2; };
 
-// Markers a Roe solve hands the CFL maximum instead of a speed when the
-// discriminant D is not a positive finite number: NH (+Inf) when D <= 0 or D
-// is NaN (no real wave speeds: the state left the hyperbolic region), NF (the
-// largest finite value) when D = +Inf (overflow).  A running maximum keeps
-// NH over NF over any speed, which is the priority the controller applies.
-template <typename T> __device__ __forceinline__ T cfl_nh() { return T(__builtin_inf()); }
-template <typename T> __device__ __forceinline__ T cfl_nf() { return sizeof(T) == 8 ? T(1.7976931348623157e308) : T(3.40282347e38f); }
-
 // Roe linearisation (Sec. 3.2).  Zbar is the arithmetic mean of
 // z = (q^1, q^2/q^1, q^3/q^1); eigenvalues of eqs. lambda1-3; eigenvectors
 // r^{1,2} = (1, s, zt (s - 2 zn)/(rho zbar (s - w))), r^3 = (0, 0, 1), where
@@ -198,12 +190,12 @@ template <typename T> __device__ __forceinline__ T cfl_nf() { return sizeof(T) =
 // Returns this interface's max_p |s^p| = c + |w| in a form the CFL reduction
 // can carry exactly -- FP64 as is; FP32 as its excess over 1, (c - 1) + |w|
 // with c - 1 = (D - 1)/(1 + c), which keeps ~1e-7 relative precision on the
-// excess (so ~1e-10 on the speed itself).  mark receives -Inf when D is a
-// positive finite number and one of the markers above otherwise; the caller
-// folds both into its maximum, so no lane branches on D.
+// excess (so ~1e-10 on the speed itself) -- and the discriminant D in D.
+// When D is not a positive finite number the returned value is meaningless
+// (FP32: always NaN); Cfl::add sorts these cases out.
 template <typename T>
 __device__ __forceinline__ T roe(T RL, T nL, T tL, T vnL, T vtL,
-                                 T RR, T nR, T tR, T vnR, T vtR, T beta, Wave<T>& w, T& mark)
+                                 T RR, T nR, T tR, T vnR, T vtR, T beta, Wave<T>& w, T& D)
 {
     // Sums of the two sides stand for the means (Zbar^1 - 1 = Sr/2, zn = Sn/2,
     // zt = St/2); every factor of 2 they introduce cancels exactly.
@@ -213,7 +205,7 @@ __device__ __forceinline__ T roe(T RL, T nL, T tL, T vnL, T vtL,
     const T h = rcp(T(2) + Sr);                   // 1 / (2 Zbar^1)
     const T wv = Sn * h;                          // w = zn / Zbar^1
     const T D1 = fma_(wv, wv - Sn, (beta - T(1)) * Sr);   // D - 1
-    const T D = T(1) + D1;                        // w^2 - 2 zn^2/Zbar^1 + Phi
+    D = T(1) + D1;                                // w^2 - 2 zn^2/Zbar^1 + Phi
     T c, ic;
     sqrt_pair(D, c, ic);
     T spd;
@@ -229,7 +221,6 @@ __device__ __forceinline__ T roe(T RL, T nL, T tL, T vnL, T vtL,
     w.a1 = T(0.5) * ic * fma_(-w.s2, d1, d2);
     w.a2 = d1 - w.a1;
     w.a3 = fma_(-w.a2, w.r2, fma_(-w.a1, w.r1, d3));
-    mark = D > T(0) ? (D < cfl_nh<T>() ? -cfl_nh<T>() : cfl_nf<T>()) : cfl_nh<T>();
     return spd;
 }
 
@@ -241,13 +232,49 @@ template <typename T> __device__ __forceinline__ double cfl_speed(T m)
     if constexpr (sizeof(T) == 8) return m;
     else return 1.0 + (double)m;
 }
-// Controller flags a reduced CFL value carries.
-template <typename T> __device__ __forceinline__ unsigned cfl_flags(T m)
-{
-    if (m == cfl_nh<T>()) return FLAG_NONHYP;
-    if (m >= cfl_nf<T>()) return FLAG_NONFINITE;
-    return 0u;
-}
+
+// Running CFL bookkeeping of one lane over the interfaces it solves: the
+// largest wave speed, and whether some discriminant D was <= 0 or NaN (no
+// real wave speeds: non-hyperbolic) or else +Inf (non-finite).
+//   FP32: a NaN-propagating maximum of the returned value (NaN exactly when
+//   D is not a positive finite number) and a NaN-propagating minimum of D --
+//   two instructions per interface, no branch.
+//   FP64: invalid interfaces enter the maximum as +Inf (non-hyperbolic) or
+//   the largest finite double (non-finite), which keeps that priority.
+template <typename T> struct Cfl;
+template <> struct Cfl<float> {
+    float m, dmin;
+    __device__ __forceinline__ Cfl() : m(-1.0f), dmin(1.0f) {}
+    __device__ __forceinline__ void add(float spd, float D)
+    {
+        m = __builtin_elementwise_maximum(m, spd);
+        dmin = __builtin_elementwise_minimum(dmin, D);
+    }
+    // This lane's contribution if it holds real interfaces (else nothing).
+    __device__ __forceinline__ void finish(bool counted, float& spd, bool& nonhyp, bool& nonfin) const
+    {
+        nonhyp = counted && !(dmin > 0.0f);
+        nonfin = counted && !nonhyp && m != m;
+        spd = (counted && m == m) ? m : -1.0f;
+    }
+};
+template <> struct Cfl<double> {
+    double m;
+    __device__ __forceinline__ Cfl() : m(0.0) {}
+    __device__ __forceinline__ void add(double spd, double D)
+    {
+        const double big = 1.7976931348623157e308, inf = __builtin_inf();
+        const bool ok = D > 0.0 && D < inf;
+        m = __builtin_fmax(m, ok ? spd : (D == inf ? big : inf));
+    }
+    __device__ __forceinline__ void finish(bool counted, double& spd, bool& nonhyp, bool& nonfin) const
+    {
+        const double big = 1.7976931348623157e308;
+        nonhyp = counted && m > big;
+        nonfin = counted && m == big;
+        spd = (counted && m < big) ? m : 0.0;
+    }
+};
 
 // MC limiter (Sec. 3.1), phi(theta) = max(0, min((1 + theta)/2, 2, 2 theta)),
 // evaluated as psi = phi/2 = max(0, min((1 + theta)/4, 1, theta)).  Halving
@@ -550,10 +577,10 @@ __device__ __forceinline__ void march(const SimDesc& d, int strip, int seg)
     const bool ghost_lo = EDGE && !perx && col == 0;        // left neighbour of this output cell is a ghost
     const bool ghost_hi = EDGE && !perx && col == nx - 1;   // right neighbour is a ghost
 
-    // Per-lane running maxima of the CFL entries, x1 and x2 interfaces
-    // apart; which lanes hold real interfaces is applied once at the end (a
-    // maximum is indifferent to order and repetition).
-    T xmax = cfl_floor<T>(), ymax = cfl_floor<T>();
+    // Per-lane CFL bookkeeping, x1 and x2 interfaces apart; which lanes hold
+    // real interfaces is applied once at the end (maxima and minima are
+    // indifferent to order and repetition).
+    Cfl<T> xacc, yacc;
 
     // ---- lean path: buffer resources over rows rs .. vlast ----
     const int rs = r0 - HALO;
@@ -605,9 +632,9 @@ __device__ __forceinline__ void march(const SimDesc& d, int strip, int seg)
         const T RL = from_lo(q.R), ML = from_lo(q.M), NL = from_lo(q.N);
         const T uL = from_lo(u), vL = from_lo(v);
         Wave<T> w;
-        T mark;
-        const T spd = roe(RL, ML, NL, uL, vL, q.R, q.M, q.N, u, v, beta, w, mark);
-        xmax = max_(max_(xmax, spd), mark);
+        T D;
+        const T spd = roe(RL, ML, NL, uL, vL, q.R, q.M, q.N, u, v, beta, w, D);
+        xacc.add(spd, D);
         // waves of the interface to the right -> products with it; the lane
         // to the left supplies the products with the interface below
         Wave<T> wr;
@@ -646,9 +673,9 @@ __device__ __forceinline__ void march(const SimDesc& d, int strip, int seg)
         const T u = q.M * irho, vv = q.N * irho;
         // x2 interface v-1/2 between rows v-1 (low) and v (high); normal = N
         Wave<T> wA;
-        T mark;
-        const T spd = roe(in.q.R, in.q.N, in.q.M, in.v, in.u, q.R, q.N, q.M, vv, u, beta, wA, mark);
-        if (LEAN || (v > vfirst && (pery || (v >= 0 && v <= ny)))) ymax = max_(max_(ymax, spd), mark);
+        T D;
+        const T spd = roe(in.q.R, in.q.N, in.q.M, in.v, in.u, q.R, q.N, q.M, vv, u, beta, wA, D);
+        if (LEAN || (v > vfirst && (pery || (v >= 0 && v <= ny)))) yacc.add(spd, D);
         T dhi[3];
         wave_dots(in.w, wA, dhi);
         dhi[2] = wA.a3;
@@ -759,7 +786,7 @@ __device__ __forceinline__ void march(const SimDesc& d, int strip, int seg)
             S a = a0, b = b0, e = e0;
             load_row(v + 2, a0, b0, e0);
             push(xsweep(v, a, b, e), v, A, B, Flag<false>{});
-            if (k == 0) ymax = cfl_floor<T>();
+            if (k == 0) yacc = Cfl<T>();
             a = a1; b = b1; e = e1;
             load_row(v + 3, a1, b1, e1);
             push(xsweep(v + 1, a, b, e), v + 1, B, A, Flag<false>{});
@@ -862,11 +889,17 @@ __device__ __forceinline__ void march(const SimDesc& d, int strip, int seg)
     // left neighbour); x2 interfaces: lanes whose x1-swept values are exact.
     const bool cnt_x = lane >= 1 && (perx || (col >= 0 && col <= nx));
     const bool cnt_y = lane >= 2 && lane <= WAVE - 3 && real_col;
-    T m = max_(cnt_x ? xmax : cfl_floor<T>(), cnt_y ? ymax : cfl_floor<T>());
+    T sx, sy;
+    bool hx, hy, fx, fy;
+    xacc.finish(cnt_x, sx, hx, fx);
+    yacc.finish(cnt_y, sy, hy, fy);
+    T m = max_(sx, sy);
     for (int off = 32; off >= 1; off >>= 1) m = max_(m, perm(m, lane ^ off));
+    const bool anyh = __any(hx || hy);
+    const bool anyf = __any(fx || fy);
     if (lane == 0) {
         atomicMax(&d.clk->smax_bits, (unsigned long long)__double_as_longlong(cfl_speed<T>(m)));
-        const unsigned fl = cfl_flags<T>(m);
+        const unsigned fl = (anyh ? FLAG_NONHYP : 0u) | (anyf ? FLAG_NONFINITE : 0u);
         if (fl) atomicOr(&d.clk->flags, fl);
     }
 }

@@ -184,30 +184,34 @@ __global__ __launch_bounds__(256) void k_dry(SimDesc d)
     const int j = blockIdx.y;
     const double t = d.clk->t;
     const T beta = (T)d.beta;
-    T sm = cfl_floor<T>();
+    Cfl<T> acc;
     if (i <= d.nx) {
         if (j < d.ny) {
             const Cell<T> a = cell_at<S, T>(d, i - 1, j, t), b = cell_at<S, T>(d, i, j, t);
             const T ia = rcp(T(1) + a.R), ib = rcp(T(1) + b.R);
             Wave<T> w;
-            T mark;
-            const T spd = roe(a.R, a.M, a.N, a.M * ia, a.N * ia, b.R, b.M, b.N, b.M * ib, b.N * ib, beta, w, mark);
-            sm = max_(max_(sm, spd), mark);
+            T D;
+            const T spd = roe(a.R, a.M, a.N, a.M * ia, a.N * ia, b.R, b.M, b.N, b.M * ib, b.N * ib, beta, w, D);
+            acc.add(spd, D);
         }
         if (i < d.nx) {
             const Cell<T> a = cell_at<S, T>(d, i, j - 1, t), b = cell_at<S, T>(d, i, j, t);
             const T ia = rcp(T(1) + a.R), ib = rcp(T(1) + b.R);
             Wave<T> w;
-            T mark;
-            const T spd = roe(a.R, a.N, a.M, a.N * ia, a.M * ia, b.R, b.N, b.M, b.N * ib, b.M * ib, beta, w, mark);
-            sm = max_(max_(sm, spd), mark);
+            T D;
+            const T spd = roe(a.R, a.N, a.M, a.N * ia, a.M * ia, b.R, b.N, b.M, b.N * ib, b.M * ib, beta, w, D);
+            acc.add(spd, D);
         }
     }
+    T sm;
+    bool nh, nf;
+    acc.finish(true, sm, nh, nf);
     const int lane = threadIdx.x & 63;
     for (int off = 32; off >= 1; off >>= 1) sm = max_(sm, perm(sm, lane ^ off));
+    const bool anyh = __any(nh), anyf = __any(nf);
     if (lane == 0) {
         atomicMax(&d.clk->smax_bits, (unsigned long long)__double_as_longlong(cfl_speed<T>(sm)));
-        const unsigned fl = cfl_flags<T>(sm);
+        const unsigned fl = (anyh ? FLAG_NONHYP : 0u) | (anyf ? FLAG_NONFINITE : 0u);
         if (fl) atomicOr(&d.clk->flags, fl);
     }
 }
