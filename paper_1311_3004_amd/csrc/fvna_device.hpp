@@ -127,9 +127,18 @@ __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x);
 __device__ __forceinline__ double sqrt_(double x) { return __builtin_sqrt(x); }
 __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
 // c = sqrt(D) and ic = 1/c: FP64 keeps the correctly rounded square root and
-// division; FP32 uses one reciprocal square root (1 ulp) and a product.
+// division; FP32 uses one reciprocal square root (1 ulp) and a product, then
+// one Newton step on c, c += (ic/2)(D - c^2).  c is the wave speed: a bias in
+// it shifts the phase of every wave a little each step, which adds up (FP32 vs
+// FP64 on the 4096^2 pulse after 2020 steps: max |dp|/p_peak 1.03e-5 without
+// the step, 8.8e-6 with it).
 __device__ __forceinline__ void sqrt_pair(double D, double& c, double& ic) { c = __builtin_sqrt(D); ic = 1.0 / c; }
-__device__ __forceinline__ void sqrt_pair(float D, float& c, float& ic) { ic = __builtin_amdgcn_rsqf(D); c = D * ic; }
+__device__ __forceinline__ void sqrt_pair(float D, float& c, float& ic)
+{
+    ic = __builtin_amdgcn_rsqf(D);
+    const float c0 = D * ic;
+    c = __builtin_fmaf(0.5f * ic, __builtin_fmaf(-c0, c0, D), c0);
+}
 __device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double abs_(double x) { return __builtin_fabs(x); }

@@ -75,7 +75,7 @@ def test_gaussian_4096_fp32_vs_fp64_2000_steps(gaussian):
     _say(f"  fp32 max |dp|/p_peak {err:.3e}")
     assert sa["steps"] == sb["steps"] == 2000
     assert abs(sa["t"] - sb["t"]) <= 1e-8 * sa["t"]
-    assert err <= 2e-5
+    assert err <= 1e-5          # the FP32 accuracy target on this workload
 
 
 def _batch_sims():
