@@ -33,12 +33,12 @@ BYTES_PER_CELL = {"f64": 48, "f32": 24, "f32_f16store": 12, "f32_bf16store": 12}
 # profiles/k_step_f32_gaussian4096.md.  Valid only for the kernel sources
 # whose SHA-256 is recorded here: any other source reports traffic null.
 PMC_TRAFFIC = {
-    "bytes_per_launch": 255.4e6 + 210.3e6,
-    "fetch_bytes": 255.4e6, "write_bytes": 210.3e6,
+    "bytes_per_launch": 250.3e6 + 208.1e6,
+    "fetch_bytes": 250.3e6, "write_bytes": 208.1e6,
     "nx": 4096, "ny": 4096,
     "sources": {
-        "fvna_device.hpp": "ae8039814e8ec79db5ea5af544ac6f6ae41e8f3453e864021d49591a48405498",
-        "fvna_runtime.hip": "e05d0474235599fd40f4f7c06913478370270e23240efefa1c31dc63f561d18a",
+        "fvna_device.hpp": "b97348f86b4e4017921cb955cca894f54e3847f00d67b9d2cfe8e5fbff8dd9c6",
+        "fvna_runtime.hip": "c43327a0bcb162e24796d89d0be34b87570b62a20c7db96470b1582820cce4b5",
     },
 }
 
