@@ -1,0 +1,86 @@
+"""Storage-precision report for the axisymmetric focused-source workloads.
+
+Runs one workload in FP64, FP32, FP16-storage and BF16-storage and prints one
+JSON line per precision: throughput (including the sampling of the final
+cycles), the focal peak pressures p+ / p- and harmonics 1..5 at the focal
+cell over the final 5 cycles, the shock-front position (steepest on-axis
+compression near the focus), and the relative errors of each against the FP64
+run.  FP16/BF16 store perturbations scaled by 64 times the source amplitude,
+so the expected peak is below 1.
+
+    python -m paper_1311_3004_amd.precision_report c3      # 8192 x 2048, 0.2 MPa, 20000 steps
+    python -m paper_1311_3004_amd.precision_report c5      # 16384 x 8192, 1 MPa, 40000 steps
+    python -m paper_1311_3004_amd.precision_report c5lite  # 8192 x 2048, 1 MPa, 20000 steps
+
+Progress goes to stdout every 2000 steps.
+"""
+import json
+import sys
+import time
+
+import numpy as np
+
+from . import diagnostics as dg
+from . import fvna, inputs
+
+PRECISIONS = ("f64", "f32", "f32_f16store", "f32_bf16store")
+
+
+def run(w, precision, steps, cycles=5):
+    med, src = w["medium"], w["source"]
+    over = {}
+    if precision in ("f32_f16store", "f32_bf16store"):
+        a = src["p_surface"] / (med["rho0"] * med["c0"] ** 2)
+        over["store_scale"] = (64 * a,) * 3
+    s = fvna.sim_from_workload(w, precision=precision, **over)
+    t0 = time.time()
+    tail = int(1.2 * cycles / src["freq"] / s.fvna_get_stats()["dt_next"]) + 10
+    done = 0
+    while steps - done > tail + 2000:
+        s.fvna_step(2000)
+        s.fvna_sync()
+        done += 2000
+        print(f"  {precision}: {done} steps, {time.time() - t0:.0f} s", flush=True)
+    t, P = dg.record_row(s, steps - done, cycles / src["freq"])
+    elapsed = time.time() - t0
+    st = s.fvna_get_stats()
+    rp, _, _ = s.fvna_get_window(0, 0, w["nx"], 1)
+    s.fvna_destroy()
+    return t, P, st, elapsed, rp[0] * med["c0"] ** 2
+
+
+def workload(which):
+    if which == "c3":
+        return inputs.c3_hifu_fp32(), 20000
+    if which == "c5lite":
+        return inputs.hifu_axisym(8192, 2048, 2e-5, 1e6, 20000, "f32"), 20000
+    if which == "c5":
+        return inputs.c5_hifu_mixed(), 40000
+    raise SystemExit(f"unknown workload {which!r} (c3, c5, c5lite)")
+
+
+def main(argv):
+    w, steps = workload(argv[1] if len(argv) > 1 else "c3")
+    freq = w["source"]["freq"]
+    ref = None
+    for prec in PRECISIONS:
+        t, P, st, elapsed, row = run(w, prec, steps)
+        summ = dg.focal_summary(t, P, freq, w["dx"], zstar=None if ref is None else ref["z_index"])
+        front = dg.shock_front(row, summ["z_index"], 300)
+        out = {"workload": w["name"], "precision": prec, "elapsed_s": elapsed,
+               "gcell_s": w["nx"] * w["ny"] * steps / elapsed / 1e9, "t_end": st["t"], "steps": st["steps"],
+               "nu_mean": st["nu_mean"], "nu_std": st["nu_std"], "z_index": summ["z_index"],
+               "p_plus": summ["p_plus"], "p_minus": summ["p_minus"],
+               "harmonics": [float(x) for x in summ["harmonics"]], "front_cells": front, "n_samples": len(t)}
+        if ref is None:
+            ref = dict(summ, front=front)
+        else:
+            out.update(dg.compare(summ, ref))
+            out["front_err_cells"] = front - ref["front"]
+            out["axis_pplus_max_rel"] = float(np.max(np.abs(summ["p_plus_axis"] - ref["p_plus_axis"]))
+                                              / np.max(ref["p_plus_axis"]))
+        print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main(sys.argv)
