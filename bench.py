@@ -10,8 +10,10 @@ centre plus 0.5% white noise (seed 2), zero-order-extrapolation sides, CFL
 Prints ONE JSON line.  Besides the headline FP32 figure it carries the FP64
 path on the same workload, the FP32 error against it, the batched form (64
 uneven simulations in one graph-replayed launch per step) against 64
-sequential launches, the roofline of the step kernel and the FP64 CPU oracle
-timed on a bounded sample on the host.
+sequential launches, the throughput of the axisymmetric focused-source
+configs (8192 x 2048 FP32; 16384 x 8192 in FP32, FP16 and BF16 storage), the
+roofline of the step kernel and the FP64 CPU oracle timed on a bounded sample
+on the host.
 """
 import argparse
 import json
@@ -90,6 +92,34 @@ def kernel_roofline(sim, precision, cells, reps=20):
     return ms, achieved
 
 
+def other_configs(fvna, inputs, steps):
+    """Throughput of the step on the axisymmetric focused-source configs: the
+    8192 x 2048 FP32 grid and the 16384 x 8192 grid in FP32, FP16 and BF16
+    storage (quiescent start, source ramping up; the cost of a step does not
+    depend on the field)."""
+    out = {}
+    runs = [("hifu-axisym 8192x2048", inputs.c3_hifu_fp32(), ("f32",))]
+    runs.append(("hifu-mixed 16384x8192", inputs.c5_hifu_mixed(), ("f32", "f32_f16store", "f32_bf16store")))
+    for name, w, precs in runs:
+        med, src = w["medium"], w["source"]
+        cells = w["nx"] * w["ny"]
+        for prec in precs:
+            over = {}
+            if "store" in prec:
+                over["store_scale"] = (64 * src["p_surface"] / (med["rho0"] * med["c0"] ** 2),) * 3
+            s = fvna.sim_from_workload(w, precision=prec, **over)
+            r = timed_run(s, steps, 10)
+            ms_k, gbs = kernel_roofline(s, prec, cells, reps=5)
+            v = cells * r["accepted"] / r["event_s"] / 1e6
+            log(f"[bench] {name} {prec}: {v:.1f} Mcell/s, kernel {ms_k:.3f} ms = {gbs:.0f} GB/s")
+            out[f"{name} {prec}"] = {"value": round(v, 1), "unit": "Mcell-updates/s", "steps": steps,
+                                     "kernel_ms": round(ms_k, 4), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                                     "tile_rows": s.fvna_get_tile_rows()}
+            s.fvna_destroy()
+        del w
+    return out
+
+
 def cpu_baseline(w, steps):
     """FP64 oracle on the host: `steps` steps of the same workload, full grid."""
     import oracle
@@ -115,6 +145,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-other", action="store_true", help="skip the axisymmetric configs")
+    ap.add_argument("--other-steps", type=int, default=200)
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--batch-steps", type=int, default=1000)
@@ -217,6 +249,9 @@ def main():
                             "hbm_frac": round(gbsb / HBM_PEAK_GBS, 4),
                             "bitwise_equal_sampled": bool(same)}
         B.fvna_batch_destroy()
+
+    if not args.no_other:
+        extra["other_configs"] = other_configs(fvna, inputs, args.other_steps)
 
     out = {
         "metric": "Mcell-updates/s and % HBM roofline, FP32/batched vs FP64 at stated error",

@@ -84,6 +84,7 @@ struct SimDesc {
     float scale[3], inv_scale[3];                        // half-width storage codec
     void* buf[2];                                        // state buffers: planes R, M, N
     Clock* clk;
+    const double* src_tab;       // focused source, per row j: frac(f r^2/(2F)), F/h, -r/h (null: none)
 };
 
 // ---------------------------------------------------------------------------
@@ -383,13 +384,16 @@ __device__ __forceinline__ void taylor_at(const SimDesc& d, double x, double y, 
     N = R * d.ta_sin;
 }
 
-// Focused source, eq. hifuBC with a sin^2 ramp: the phase f (t + r^2/(2F)) is
-// reduced modulo one period in FP64 before the sine.
-template <typename T>
-__device__ __forceinline__ void source_at(const SimDesc& d, double r, double t, T& R, T& M, T& N)
+// Focused source, eq. hifuBC with a sin^2 ramp.  The parts that depend on
+// time only -- the ramp envelope and f t reduced modulo one period -- are
+// evaluated once per wavefront and step (source_clock); the parts that depend
+// on the row only -- the focusing delay f r^2/(2F) reduced modulo one period
+// and the direction cosines F/h, -r/h with h = sqrt(r^2 + F^2) -- come from a
+// table filled when the source is set.  The phase is their sum reduced again,
+// in FP64, before the sine.
+__device__ __forceinline__ void source_clock(const SimDesc& d, double t, double& ft, double& env)
 {
     const double f = d.sr_freq;
-    double env;
     if (t <= 0.0) {
         env = 0.0;
     } else if (t < d.sr_ramp / f) {
@@ -398,15 +402,27 @@ __device__ __forceinline__ void source_at(const SimDesc& d, double r, double t, 
     } else {
         env = 1.0;
     }
-    double ph = f * (t + r * r / (2.0 * d.sr_F));
+    ft = f * t;
+    ft -= floor(ft);
+}
+
+template <typename T>
+__device__ __forceinline__ void source_at(const SimDesc& d, int j, double ft, double env, T& R, T& M, T& N)
+{
+    if (!d.src_tab) { R = M = N = T(0); return; }
+    // read-only during a step and indexed by a wave-uniform row: through the
+    // constant address space these are scalar loads, which do not wait behind
+    // the row loads in flight
+    typedef const __attribute__((address_space(4))) double* ConstRow;
+    const ConstRow e = (ConstRow)(d.src_tab + 3 * (size_t)j);
+    double ph = ft + e[0];
     ph -= floor(ph);
     T g;
     if constexpr (sizeof(T) == 8) g = (T)(d.sr_amp * env * sin(2.0 * M_PI * ph));
     else g = (T)(d.sr_amp * env) * __sinf((float)(2.0 * M_PI * ph));
-    const double h = sqrt(r * r + d.sr_F * d.sr_F);
     R = g;
-    M = g * (T)(d.sr_F / h);
-    N = g * (T)(-r / h);
+    M = g * (T)e[1];
+    N = g * (T)e[2];
 }
 
 // ---------------------------------------------------------------------------
@@ -554,6 +570,8 @@ __device__ __forceinline__ void march(const SimDesc& d, int strip, int seg)
     const T hdt = T(0.5) * dt;
     const float sc0 = d.scale[0], sc1 = d.scale[1], sc2 = d.scale[2];
     const float is0 = d.inv_scale[0], is1 = d.inv_scale[1], is2 = d.inv_scale[2];
+    double src_ft = 0.0, src_env = 0.0;          // focused source at this step's time
+    if (EDGE && d.bc[0] == BC_SOURCE) source_clock(d, tn, src_ft, src_env);
 
     // ---- where this lane's Q^n comes from (x boundary rule) ----
     const bool incol = col >= 0 && col < nx;
@@ -632,8 +650,7 @@ __device__ __forceinline__ void march(const SimDesc& d, int strip, int seg)
                 taylor_at(d, col + 0.5, vr + 0.5, tn, R, M, N);
                 q.R = (T)R; q.M = (T)M; q.N = (T)N;
             } else if (xkind == 2) {
-                const double r = vr + 0.5;
-                if (r <= d.sr_ap) source_at<T>(d, r, tn, q.R, q.M, q.N);
+                if (vr + 0.5 <= d.sr_ap) source_at<T>(d, vr, src_ft, src_env, q.R, q.M, q.N);
             }
         }
         const T irho = rcp(T(1) + q.R);
@@ -718,7 +735,7 @@ __device__ __forceinline__ void march(const SimDesc& d, int strip, int seg)
                     else if (b == BC_TAYLOR) taylor_uv(-0.5, j + 0.5, uxl, vxl);
                     else if (b == BC_SOURCE && j + 0.5 <= d.sr_ap) {
                         T R, M, N;
-                        source_at<T>(d, j + 0.5, tn, R, M, N);
+                        source_at<T>(d, j, src_ft, src_env, R, M, N);
                         const T ir = rcp(T(1) + R);
                         uxl = M * ir; vxl = N * ir;
                     } else { uxl = in.us; vxl = in.vs; }

@@ -148,7 +148,9 @@ __device__ Cell<T> cell_at(const SimDesc& d, int i, int j, double t)
         }
         if (b == BC_SOURCE && (j + 0.5) <= d.sr_ap) {
             Cell<T> q;
-            source_at<T>(d, j + 0.5, t, q.R, q.M, q.N);
+            double ft, env;
+            source_clock(d, t, ft, env);
+            source_at<T>(d, j, ft, env, q.R, q.M, q.N);
             return q;
         }
         if (b == BC_PERIODIC) {
@@ -382,11 +384,16 @@ size_t state_bytes_of(const fvna_params* p)
     return align_up((size_t)3 * (size_t)pitch_of(p) * (size_t)p->ny * elem_size(p->precision), ALIGN);
 }
 
-// scratch layout: [Clock][sum partials][sum out][staging]
+// scratch layout: [Clock][sum partials][sum out][source table][staging]
 constexpr size_t OFF_CLOCK = 0;
 constexpr size_t OFF_PART = 256;
 constexpr size_t OFF_SUMOUT = OFF_PART + align_up(SUM_BLOCKS * 3 * sizeof(double), ALIGN);
-constexpr size_t OFF_STAGE = OFF_SUMOUT + 256;
+constexpr size_t OFF_SRCTAB = OFF_SUMOUT + 256;
+
+size_t stage_off_of(const fvna_params* p)
+{
+    return OFF_SRCTAB + align_up(3 * (size_t)p->ny * sizeof(double), ALIGN);
+}
 
 size_t stage_cells_of(const fvna_params* p)
 {
@@ -396,7 +403,7 @@ size_t stage_cells_of(const fvna_params* p)
 
 size_t scratch_bytes_of(const fvna_params* p)
 {
-    return OFF_STAGE + align_up(stage_cells_of(p) * sizeof(double), ALIGN);
+    return stage_off_of(p) + align_up(stage_cells_of(p) * sizeof(double), ALIGN);
 }
 
 // Rows per wavefront segment when none is given: enough segments that the
@@ -673,6 +680,22 @@ fvna_status fvna_set_source(fvna_ctx* c, int32_t side, const fvna_source* s)
     c->d.sr_F = s->focal_length / p.dx;
     c->d.sr_ap = s->aperture / p.dx;
     c->d.sr_ramp = s->ramp_cycles;
+    // per-row table: focusing delay (reduced modulo one period) and direction cosines
+    std::vector<double> tab(3 * (size_t)p.ny);
+    const double f = c->d.sr_freq, F = c->d.sr_F;
+    for (int j = 0; j < p.ny; ++j) {
+        const double r = j + 0.5;
+        double ph = f * (r * r / (2.0 * F));
+        ph -= std::floor(ph);
+        const double h = std::sqrt(r * r + F * F);
+        tab[3 * (size_t)j] = ph;
+        tab[3 * (size_t)j + 1] = F / h;
+        tab[3 * (size_t)j + 2] = -r / h;
+    }
+    double* dtab = (double*)(c->scratch + OFF_SRCTAB);
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipMemcpy(dtab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice));
+    c->d.src_tab = dtab;
     drop_graph(c);
     return FVNA_OK;
 }
@@ -698,7 +721,7 @@ fvna_status fvna_set_state(fvna_ctx* c, const double* rho_p, const double* mom_x
 {
     if (!c || !rho_p || !mom_x || !mom_y) return fail(FVNA_E_INVALID, "NULL argument");
     const fvna_params& p = c->p;
-    double* stage = (double*)(c->scratch + OFF_STAGE);
+    double* stage = (double*)(c->scratch + stage_off_of(&c->p));
     const size_t chunk_rows = std::max<size_t>(1, stage_cells_of(&p) / (size_t)p.nx);
     const double denom[3] = {p.rho0, p.rho0 * p.c0, p.rho0 * p.c0};
     const double* src[3] = {rho_p, mom_x, mom_y};
@@ -772,7 +795,7 @@ static fvna_status export_window(fvna_ctx* c, int i0, int j0, int ni, int nj, do
                                  double* mom_y)
 {
     const fvna_params& p = c->p;
-    double* stage = (double*)(c->scratch + OFF_STAGE);
+    double* stage = (double*)(c->scratch + stage_off_of(&c->p));
     const size_t chunk_rows = std::max<size_t>(1, stage_cells_of(&p) / (size_t)ni);
     const double factor[3] = {p.rho0, p.rho0 * p.c0, p.rho0 * p.c0};
     double* dst[3] = {rho_p, mom_x, mom_y};
