@@ -123,7 +123,18 @@ template <> struct Codec<bf16, float> {
 // ---------------------------------------------------------------------------
 // Arithmetic helpers per compute type.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+// FP64 reciprocal: the hardware estimate refined by two Newton steps
+// (r += r (1 - x r)), within an ulp of 1/x for the finite non-zero x the
+// step divides by; 1/0 gives NaN instead of Inf, which the limiter treats
+// exactly as it treats 0 * Inf (its wave strength is zero).  The square root
+// and 1/c that set the wave speeds stay correctly rounded (sqrt_pair).
+__device__ __forceinline__ double rcp(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = __builtin_fma(__builtin_fma(-x, r, 1.0), r, r);
+    r = __builtin_fma(__builtin_fma(-x, r, 1.0), r, r);
+    return r;
+}
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double sqrt_(double x) { return __builtin_sqrt(x); }
 __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
