@@ -145,7 +145,10 @@ fvna_status fvna_create(const fvna_params* p, void* state_a, void* state_b, void
  * axisymmetric geometry needs REFLECT on side 2. */
 fvna_status fvna_set_bc(fvna_ctx* c, int32_t side, int32_t bc);
 
-/* Parameters of the focused source (side must be 0). */
+/* Parameters of the focused source (side must be 0).  Fills the per-row
+ * table of the source (focusing delay and direction cosines, in the scratch
+ * buffer) with a synchronous copy: waits for the context's stream first.
+ * Until it is called, a SOURCE side holds zero ghost cells. */
 fvna_status fvna_set_source(fvna_ctx* c, int32_t side, const fvna_source* s);
 
 /* Parameters of the Taylor profile used by TAYLOR sides (eq. OurTaylorS with
