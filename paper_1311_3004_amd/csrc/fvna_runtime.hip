@@ -39,29 +39,38 @@ using namespace fvna;
 __device__ void control(const SimDesc& d)
 {
     Clock* c = d.clk;
-    if (c->status != 0 || c->accepted >= c->target) return;
-    c->attempts++;
-    const double smax = __longlong_as_double((long long)atomicExch(&c->smax_bits, 0ull));
+    // All memory traffic is issued at once, so the launch costs one round
+    // trip: the attempt's largest speed and flags are taken (and cleared for
+    // the next attempt) whether or not the attempt counts -- a step launch
+    // that had nothing to do left them at zero.
+    const unsigned long long sb = atomicExch(&c->smax_bits, 0ull);
     const unsigned flags = atomicExch(&c->flags, 0u);
-    if (flags & FLAG_NONHYP) { c->status = ST_NONHYP; c->status_step = c->accepted; return; }
-    if ((flags & FLAG_NONFINITE) || !(smax <= DBL_MAX)) { c->status = ST_NONFINITE; c->status_step = c->accepted; return; }
-    const double nu = c->dt * smax;
+    const Clock h = *c;
+    if (h.status != 0 || h.accepted >= h.target) return;
+    const double smax = __longlong_as_double((long long)sb);
+    c->attempts = h.attempts + 1;
+    if (flags & FLAG_NONHYP) { c->status = ST_NONHYP; c->status_step = h.accepted; return; }
+    if ((flags & FLAG_NONFINITE) || !(smax <= DBL_MAX)) { c->status = ST_NONFINITE; c->status_step = h.accepted; return; }
+    const double nu = h.dt * smax;
     c->nu_last = nu;
     if (!d.fixed_dt && nu > d.cfl_max) {
-        c->rejected++;
-        if (++c->retries > d.max_retries) { c->status = ST_RETRIES; c->status_step = c->accepted; return; }
-        c->dt = c->dt * d.cfl_target / nu;
+        c->rejected = h.rejected + 1;
+        c->retries = h.retries + 1;
+        if (h.retries + 1 > d.max_retries) { c->status = ST_RETRIES; c->status_step = h.accepted; return; }
+        c->dt = h.dt * d.cfl_target / nu;
         return;
     }
     c->retries = 0;
-    c->t = c->t + c->dt;
-    c->accepted++;
-    c->cur ^= 1;
-    c->nu_count++;
-    const double dev = nu - c->nu_mean;
-    c->nu_mean = c->nu_mean + dev / (double)c->nu_count;
-    c->nu_m2 = c->nu_m2 + dev * (nu - c->nu_mean);
-    if (!d.fixed_dt && smax > 0.0) c->dt = c->dt * d.cfl_target / nu;
+    c->t = h.t + h.dt;
+    c->accepted = h.accepted + 1;
+    c->cur = h.cur ^ 1;
+    const long long n = h.nu_count + 1;
+    c->nu_count = n;
+    const double dev = nu - h.nu_mean;
+    const double mean = h.nu_mean + dev / (double)n;
+    c->nu_mean = mean;
+    c->nu_m2 = h.nu_m2 + dev * (nu - mean);
+    if (!d.fixed_dt && smax > 0.0) c->dt = h.dt * d.cfl_target / nu;
 }
 
 __global__ void k_ctrl(SimDesc d)
@@ -120,7 +129,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occupancy<T
 void k_step_batch(const SimDesc* __restrict__ descs, const TileRef* __restrict__ tiles, int ntiles, int force)
 {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int tile = blockIdx.x * WAVES_PER_BLOCK + wave;
+    const int tile = xcd_block(blockIdx.x, gridDim.x) * WAVES_PER_BLOCK + wave;
     if (tile >= ntiles) return;
     const TileRef tr = tiles[tile];
     const SimDesc& d = descs[tr.sim];
