@@ -35,12 +35,12 @@ BYTES_PER_CELL = {"f64": 48, "f32": 24, "f32_f16store": 12, "f32_bf16store": 12}
 # profiles/k_step_f32_gaussian4096.md.  Valid only for the kernel sources
 # whose SHA-256 is recorded here: any other source reports traffic null.
 PMC_TRAFFIC = {
-    "bytes_per_launch": 250.3e6 + 208.1e6,
-    "fetch_bytes": 250.3e6, "write_bytes": 208.1e6,
+    "bytes_per_launch": 216.0e6 + 203.1e6,
+    "fetch_bytes": 216.0e6, "write_bytes": 203.1e6,
     "nx": 4096, "ny": 4096,
     "sources": {
-        "fvna_device.hpp": "b97348f86b4e4017921cb955cca894f54e3847f00d67b9d2cfe8e5fbff8dd9c6",
-        "fvna_runtime.hip": "c43327a0bcb162e24796d89d0be34b87570b62a20c7db96470b1582820cce4b5",
+        "fvna_device.hpp": "7c96efe35ae5fac3dc2742e804ad11a40453db74771b419d6ddd2b66ed13687b",
+        "fvna_runtime.hip": "d7426fae7927e0d4828670523dc893a5bc0fff7b74b2ff57ce0bef409e64bd85",
     },
 }
 
