@@ -205,8 +205,8 @@ def main():
     # ---- batched form: 64 uneven simulations vs 64 sequential runs ----
     if not args.no_batch:
         sims = inputs.c4_batch()
-        plist = [fvna.make_params(x["nx"], x["ny"], x["dx"], x["medium"], bc=x["bc"], precision="f32",
-                                  tile_rows=tile_rows) for x in sims]
+        plist = [fvna.make_params(x["nx"], x["ny"], x["dx"], x["medium"], bc=x["bc"], precision="f32")
+                 for x in sims]
         B = fvna.Batch(plist)
         for k, x in enumerate(sims):
             B.fvna_batch_set_state(k, *x["state"])

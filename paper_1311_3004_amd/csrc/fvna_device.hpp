@@ -109,13 +109,10 @@ template <> struct Codec<bf16, float> {
     static __device__ __forceinline__ float ld(bf16 s, float scale) {
         return __uint_as_float((uint32_t)s.bits << 16) * scale;
     }
+    // round to nearest, ties to even, by gfx950's v_cvt_pk_bf16_f32
     static __device__ __forceinline__ bf16 st(float v, float inv) {
-        float x = v * inv;
-        uint32_t b = __float_as_uint(x);
         bf16 r;
-        if ((b & 0x7fffffffu) > 0x7f800000u) { r.bits = (uint16_t)((b >> 16) | 0x40u); return r; }  // quiet NaN
-        b += 0x7fffu + ((b >> 16) & 1u);   // round to nearest, ties to even
-        r.bits = (uint16_t)(b >> 16);
+        r.bits = __builtin_bit_cast(uint16_t, (__bf16)(v * inv));
         return r;
     }
 };

@@ -350,6 +350,10 @@ fvna_status fail(fvna_status s, const std::string& msg)
 constexpr size_t ALIGN = 256;
 constexpr size_t STAGE_CELLS = size_t(1) << 20;   // staging chunk for set/get state
 constexpr int GRAPH_CHUNK = 32;                   // attempts per captured graph
+// Segment height of batched simulations without their own: the batch runs in
+// several rounds of wavefronts, so the one-round rule of a single grid does not
+// apply; 128 rows measured best on 64 uneven grids (48..256 tried).
+constexpr int BATCH_TILE_ROWS = 128;
 
 constexpr size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -1076,7 +1080,7 @@ fvna_status fvna_batch_create(int32_t n, const fvna_params* per_sim, void* const
         b->p.push_back(p);
         SimDesc d;
         // many simulations fill the device in many rounds: moderate segments
-        int tr = p.tile_rows ? p.tile_rows : 96;
+        int tr = p.tile_rows ? p.tile_rows : BATCH_TILE_ROWS;
         char* sc = (char*)bufs[3 * k + 2];
         fill_desc(d, &p, bufs[3 * k], bufs[3 * k + 1], (Clock*)(sc + OFF_CLOCK), tr);
         b->d.push_back(d);
