@@ -36,6 +36,7 @@ class Params(ctypes.Structure):
         ("src_amp", ctypes.c_double), ("src_freq", ctypes.c_double),
         ("src_focal", ctypes.c_double), ("src_aperture", ctypes.c_double),
         ("src_ramp_cycles", ctypes.c_double),
+        ("src_envelope", ctypes.c_int), ("src_packet_cycles", ctypes.c_double),
     ]
 
 
@@ -124,7 +125,8 @@ def make_params(nx, ny, beta, delta, bc=("extrap0",) * 4, geometry="planar",
                 taylor=None, source=None):
     """Dimensionless parameters.  delta is delta~ = delta/(c0 dx).  taylor: dict
     amp, width, x0, y0, angle (cells).  source: dict amp, freq (cycles per
-    dx/c0), focal, aperture (cells), ramp_cycles."""
+    dx/c0), focal, aperture (cells), ramp_cycles, envelope ("ramp" or
+    "packet"), packet_cycles."""
     p = Params()
     p.nx, p.ny = int(nx), int(ny)
     p.beta, p.delta = float(beta), float(delta)
@@ -141,6 +143,8 @@ def make_params(nx, ny, beta, delta, bc=("extrap0",) * 4, geometry="planar",
     p.src_amp = float(s.get("amp", 0.0)); p.src_freq = float(s.get("freq", 1.0))
     p.src_focal = float(s.get("focal", 1e30)); p.src_aperture = float(s.get("aperture", 0.0))
     p.src_ramp_cycles = float(s.get("ramp_cycles", 3.0))
+    p.src_envelope = {"ramp": 0, "packet": 1}[s.get("envelope", "ramp")]
+    p.src_packet_cycles = float(s.get("packet_cycles", 4.0))
     return p
 
 
@@ -161,7 +165,9 @@ def make_params_si(nx, ny, dx, c0, rho0, beta, delta, bc=("extrap0",) * 4, geome
     if source_si is not None:
         source = {"amp": source_si["p_surface"] / p0, "freq": source_si["freq"] * dx / c0,
                   "focal": source_si["focal_length"] / dx, "aperture": source_si["aperture"] / dx,
-                  "ramp_cycles": source_si.get("ramp_cycles", 3.0)}
+                  "ramp_cycles": source_si.get("ramp_cycles", 3.0),
+                  "envelope": source_si.get("envelope", "ramp"),
+                  "packet_cycles": source_si.get("packet_cycles", 4.0)}
     return make_params(nx, ny, beta, delta / (c0 * dx), bc, geometry, cfl_target, cfl_max,
                        max_retries, fixed_dt, taylor, source)
 

@@ -54,6 +54,9 @@ typedef struct {
     double taylor_amp, taylor_width, taylor_x0, taylor_y0, taylor_angle;
     /* focused boundary source used by BC_SOURCE on side x- (eq. hifuBC)      */
     double src_amp, src_freq, src_focal, src_aperture, src_ramp_cycles;
+    int src_envelope;         /* 0: sin^2 ramp over src_ramp_cycles periods from t = 0;
+                                 1: the packet of eq. hifuBC:g, width src_packet_cycles */
+    double src_packet_cycles;
 } orc_params;
 
 typedef struct {
@@ -291,17 +294,26 @@ static void taylor_value(const orc_params *p, double x, double y, double t, doub
     q[0] = R; q[1] = R * ca; q[2] = R * sa;
 }
 
-/* Focused boundary source (eq. hifuBC) at distance r from the symmetry line,
- * with the envelope replaced by a sin^2 ramp over src_ramp_cycles periods. */
+/* Focused boundary source (eq. hifuBC) at distance r from the symmetry line:
+ * g = A sin(2 pi f tau) env, tau = t + r^2/(2F).  Envelope 1 is the paper's
+ * packet of eq. hifuBC:g, read as exp(-(f tau / W)^10) with W periods (the
+ * printed exponent -10 would make a hole around tau = 0 instead of a packet
+ * centred there); envelope 0 replaces it by a sin^2 ramp in t over
+ * src_ramp_cycles periods, for a continuous focused field. */
 static double source_g(const orc_params *p, double r, double t)
 {
     double f = p->src_freq;
     double tau = t + r * r / (2.0 * p->src_focal);
     double env;
-    double tr = p->src_ramp_cycles / f;
-    if (t <= 0.0) env = 0.0;
-    else if (t < tr) { double s = sin(M_PI * f * t / (2.0 * p->src_ramp_cycles)); env = s * s; }
-    else env = 1.0;
+    if (p->src_envelope == 1) {
+        double x = f * tau / p->src_packet_cycles;
+        env = exp(-pow(x, 10.0));
+    } else {
+        double tr = p->src_ramp_cycles / f;
+        if (t <= 0.0) env = 0.0;
+        else if (t < tr) { double s = sin(M_PI * f * t / (2.0 * p->src_ramp_cycles)); env = s * s; }
+        else env = 1.0;
+    }
     return p->src_amp * env * sin(2.0 * M_PI * f * tau);
 }
 
@@ -533,6 +545,8 @@ static int check_params(const orc_params *p)
     for (int s = 0; s < 4; s++) if (p->bc[s] < 0 || p->bc[s] > BC_SOURCE) return ORC_E_INVALID;
     if ((p->bc[0] == BC_PERIODIC) != (p->bc[1] == BC_PERIODIC)) return ORC_E_INVALID;
     if ((p->bc[2] == BC_PERIODIC) != (p->bc[3] == BC_PERIODIC)) return ORC_E_INVALID;
+    if (p->src_envelope < 0 || p->src_envelope > 1) return ORC_E_INVALID;
+    if (p->src_envelope == 1 && !(p->src_packet_cycles > 0.0)) return ORC_E_INVALID;
     return ORC_OK;
 }
 

@@ -519,3 +519,42 @@ def test_travelling_speed_matches_rankine_hugoniot():
     # mass: V [R] = [M];  momentum: V [M] = [u^2 + phi]
     assert abs(V * (RL - RR) - ML) < 1e-15
     assert abs(V * ML - (flux_mom(ML, uL, RL) - flux_mom(0.0, 0.0, RR))) < 1e-15
+
+
+# -- Focused source with the packet envelope (eq. hifuBC, reading A10) ----------
+
+def test_packet_source_launches_the_packet_as_a_plane_wave(orc):
+    """With an unfocused source covering the whole side (F -> inf, aperture
+    beyond the grid) eq. hifuBC imposes q1 - 1 = q2 = g(t) at x1 = 0: a plane
+    packet g = A sin(2 pi f t) exp(-(f t / W)^10) that, at small amplitude,
+    propagates at c0.  The time series at a probe 80 cells in must match g
+    delayed by the travel time (fitted; the face sits between 80 and 81.5
+    cells away) to within 3% of A, with M = R (right-going) and N = 0.  A
+    wrong envelope exponent or width, time origin, phase factor or sign of q2
+    fails this."""
+    eta, W, A = 40.0, 4.0, 1e-6
+    f = 1.0 / eta
+    p = orc.make_params(120, 4, 4.8, 0.0, bc=("source", "extrap0", "periodic", "periodic"),
+                        source={"amp": A, "freq": f, "focal": 1e30, "aperture": 1e9,
+                                "envelope": "packet", "packet_cycles": W})
+    R = np.zeros((4, 120)); M = R.copy(); N = R.copy()
+    t, dt = -6.0 / f, 0.0                 # start 6 periods before the packet centre
+    ts, rs, ms, ns = [], [], [], []
+    while t < 80.0 + 6.5 / f:
+        R, M, N, info = orc.run(p, R, M, N, 1, t=t, dt=dt)
+        assert info["status"] == 0
+        t, dt = info["t"], info["dt_next"]
+        ts.append(t); rs.append(R[0, 80]); ms.append(M[0, 80]); ns.append(N[0, 80])
+    ts, rs, ms, ns = map(np.array, (ts, rs, ms, ns))
+
+    def g(tt):
+        return A * np.sin(2 * np.pi * f * tt) * np.exp(-(f * tt / W) ** 10)
+
+    delays = np.linspace(79.0, 83.0, 401)
+    errs = [np.max(np.abs(rs - g(ts - dly))) for dly in delays]
+    k = int(np.argmin(errs))
+    assert 80.0 <= delays[k] <= 81.5, delays[k]
+    assert errs[k] <= 0.03 * A, errs[k] / A
+    assert np.max(np.abs(ms - rs)) <= 0.03 * A
+    assert np.max(np.abs(ns)) <= 1e-3 * A
+    assert abs(np.max(np.abs(rs)) / A - 1.0) < 0.03      # flat top at full amplitude
