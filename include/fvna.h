@@ -101,18 +101,28 @@ typedef struct {
     int32_t tile_rows;         /* rows per wavefront segment; 0 = library default */
 } fvna_params;
 
-/* Focused boundary source of eq. hifuBC, adapted: on side x-, for the ghost
- * rows whose centre r (distance from side y-) is <= aperture,
+/* Focused boundary source of eq. hifuBC on side x-: for the ghost rows whose
+ * centre r (distance from side y-) is <= aperture,
  *   R = g, M = F g / sqrt(r^2 + F^2), N = -r g / sqrt(r^2 + F^2),
- *   g = (p_surface / (rho0 c0^2)) w(t) sin(2 pi freq (t + r^2 / (2 F c0))),
- *   w(t) = sin^2(pi freq t / (2 ramp_cycles)) for 0 < t < ramp_cycles/freq,
- *          0 for t <= 0, 1 afterwards. */
+ *   g = (p_surface / (rho0 c0^2)) w sin(2 pi freq tau),  tau = t + r^2 / (2 F c0),
+ * with the envelope w chosen by `envelope`:
+ *   FVNA_ENV_RAMP:   w(t) = sin^2(pi freq t / (2 ramp_cycles)) for
+ *                    0 < t < ramp_cycles/freq, 0 for t <= 0, 1 afterwards
+ *                    (a continuous focused field; not in the paper);
+ *   FVNA_ENV_PACKET: w = exp(-(freq tau / packet_cycles)^10), the packet of
+ *                    eq. hifuBC:g (exponent read as +10: a flat-top packet of
+ *                    half-width packet_cycles periods centred on tau = 0; the
+ *                    paper uses 4 and starts the run at a negative time, see
+ *                    fvna_set_clock). */
+typedef enum { FVNA_ENV_RAMP = 0, FVNA_ENV_PACKET = 1 } fvna_envelope;
 typedef struct {
     double freq;               /* [Hz] > 0 */
     double p_surface;          /* [Pa] */
     double focal_length;       /* F [m] > 0 */
     double aperture;           /* [m] >= 0 */
-    double ramp_cycles;        /* > 0 */
+    double ramp_cycles;        /* > 0 (FVNA_ENV_RAMP) */
+    int32_t envelope;          /* fvna_envelope */
+    double packet_cycles;      /* > 0 (FVNA_ENV_PACKET) */
 } fvna_source;
 
 typedef struct {

@@ -84,7 +84,9 @@ struct SimDesc {
     float scale[3], inv_scale[3];                        // half-width storage codec
     void* buf[2];                                        // state buffers: planes R, M, N
     Clock* clk;
-    const double* src_tab;       // focused source, per row j: frac(f r^2/(2F)), F/h, -r/h (null: none)
+    const double* src_tab;       // focused source, per row j: frac(f r^2/(2F)), F/h, -r/h, f r^2/(2F) (null: none)
+    int sr_env;                  // 0: sin^2 ramp in t; 1: packet exp(-(f tau / sr_W)^10)
+    double sr_W;                 // packet half-width in periods
 };
 
 // ---------------------------------------------------------------------------
@@ -392,39 +394,50 @@ __device__ __forceinline__ void taylor_at(const SimDesc& d, double x, double y, 
     N = R * d.ta_sin;
 }
 
-// Focused source, eq. hifuBC with a sin^2 ramp.  The parts that depend on
-// time only -- the ramp envelope and f t reduced modulo one period -- are
-// evaluated once per wavefront and step (source_clock); the parts that depend
-// on the row only -- the focusing delay f r^2/(2F) reduced modulo one period
-// and the direction cosines F/h, -r/h with h = sqrt(r^2 + F^2) -- come from a
-// table filled when the source is set.  The phase is their sum reduced again,
-// in FP64, before the sine.
-__device__ __forceinline__ void source_clock(const SimDesc& d, double t, double& ft, double& env)
+// Focused source, eq. hifuBC.  The parts that depend on time only -- the
+// ramp envelope and f t, whole and reduced modulo one period -- are evaluated
+// once per wavefront and step (source_clock); the parts that depend on the
+// row only -- the focusing delay f r^2/(2F), whole and reduced modulo one
+// period, and the direction cosines F/h, -r/h with h = sqrt(r^2 + F^2) --
+// come from a table filled when the source is set.  The sine's phase is the
+// sum of the reduced parts reduced again, in FP64; the packet envelope of eq.
+// hifuBC:g, exp(-(f tau / W)^10), takes the whole f tau.
+struct SourceClock { double ft_frac, ft, env; };
+
+__device__ __forceinline__ SourceClock source_clock(const SimDesc& d, double t)
 {
+    SourceClock c;
     const double f = d.sr_freq;
     if (t <= 0.0) {
-        env = 0.0;
+        c.env = 0.0;
     } else if (t < d.sr_ramp / f) {
         const double s = sin(M_PI * f * t / (2.0 * d.sr_ramp));
-        env = s * s;
+        c.env = s * s;
     } else {
-        env = 1.0;
+        c.env = 1.0;
     }
-    ft = f * t;
-    ft -= floor(ft);
+    c.ft = f * t;
+    c.ft_frac = c.ft - floor(c.ft);
+    return c;
 }
 
 template <typename T>
-__device__ __forceinline__ void source_at(const SimDesc& d, int j, double ft, double env, T& R, T& M, T& N)
+__device__ __forceinline__ void source_at(const SimDesc& d, int j, const SourceClock& sc, T& R, T& M, T& N)
 {
     if (!d.src_tab) { R = M = N = T(0); return; }
     // read-only during a step and indexed by a wave-uniform row: through the
     // constant address space these are scalar loads, which do not wait behind
     // the row loads in flight
     typedef const __attribute__((address_space(4))) double* ConstRow;
-    const ConstRow e = (ConstRow)(d.src_tab + 3 * (size_t)j);
-    double ph = ft + e[0];
+    const ConstRow e = (ConstRow)(d.src_tab + 4 * (size_t)j);
+    double ph = sc.ft_frac + e[0];
     ph -= floor(ph);
+    double env = sc.env;
+    if (d.sr_env == 1) {
+        const double x = (sc.ft + e[3]) / d.sr_W;
+        const double x2 = x * x, x4 = x2 * x2, x8 = x4 * x4;
+        env = exp(-(x8 * x2));
+    }
     T g;
     if constexpr (sizeof(T) == 8) g = (T)(d.sr_amp * env * sin(2.0 * M_PI * ph));
     else g = (T)(d.sr_amp * env) * __sinf((float)(2.0 * M_PI * ph));
@@ -578,8 +591,8 @@ __device__ __forceinline__ void march(const SimDesc& d, int strip, int seg)
     const T hdt = T(0.5) * dt;
     const float sc0 = d.scale[0], sc1 = d.scale[1], sc2 = d.scale[2];
     const float is0 = d.inv_scale[0], is1 = d.inv_scale[1], is2 = d.inv_scale[2];
-    double src_ft = 0.0, src_env = 0.0;          // focused source at this step's time
-    if (EDGE && d.bc[0] == BC_SOURCE) source_clock(d, tn, src_ft, src_env);
+    SourceClock src_clk = {0.0, 0.0, 0.0};       // focused source at this step's time
+    if (EDGE && d.bc[0] == BC_SOURCE) src_clk = source_clock(d, tn);
 
     // ---- where this lane's Q^n comes from (x boundary rule) ----
     const bool incol = col >= 0 && col < nx;
@@ -658,7 +671,7 @@ __device__ __forceinline__ void march(const SimDesc& d, int strip, int seg)
                 taylor_at(d, col + 0.5, vr + 0.5, tn, R, M, N);
                 q.R = (T)R; q.M = (T)M; q.N = (T)N;
             } else if (xkind == 2) {
-                if (vr + 0.5 <= d.sr_ap) source_at<T>(d, vr, src_ft, src_env, q.R, q.M, q.N);
+                if (vr + 0.5 <= d.sr_ap) source_at<T>(d, vr, src_clk, q.R, q.M, q.N);
             }
         }
         const T irho = rcp(T(1) + q.R);
@@ -743,7 +756,7 @@ __device__ __forceinline__ void march(const SimDesc& d, int strip, int seg)
                     else if (b == BC_TAYLOR) taylor_uv(-0.5, j + 0.5, uxl, vxl);
                     else if (b == BC_SOURCE && j + 0.5 <= d.sr_ap) {
                         T R, M, N;
-                        source_at<T>(d, j, src_ft, src_env, R, M, N);
+                        source_at<T>(d, j, src_clk, R, M, N);
                         const T ir = rcp(T(1) + R);
                         uxl = M * ir; vxl = N * ir;
                     } else { uxl = in.us; vxl = in.vs; }

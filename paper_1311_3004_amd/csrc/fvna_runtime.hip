@@ -172,9 +172,7 @@ __device__ Cell<T> cell_at(const SimDesc& d, int i, int j, double t)
         }
         if (b == BC_SOURCE && (j + 0.5) <= d.sr_ap) {
             Cell<T> q;
-            double ft, env;
-            source_clock(d, t, ft, env);
-            source_at<T>(d, j, ft, env, q.R, q.M, q.N);
+            source_at<T>(d, j, source_clock(d, t), q.R, q.M, q.N);
             return q;
         }
         if (b == BC_PERIODIC) {
@@ -420,7 +418,7 @@ constexpr size_t OFF_SRCTAB = OFF_SUMOUT + 256;
 
 size_t stage_off_of(const fvna_params* p)
 {
-    return OFF_SRCTAB + align_up(3 * (size_t)p->ny * sizeof(double), ALIGN);
+    return OFF_SRCTAB + align_up(4 * (size_t)p->ny * sizeof(double), ALIGN);
 }
 
 size_t stage_cells_of(const fvna_params* p)
@@ -700,25 +698,35 @@ fvna_status fvna_set_source(fvna_ctx* c, int32_t side, const fvna_source* s)
 {
     if (!c || !s) return fail(FVNA_E_INVALID, "NULL argument");
     if (side != 0) return fail(FVNA_E_INVALID, "the focused source is only available on side x-");
-    if (!(s->freq > 0) || !(s->focal_length > 0) || !(s->aperture >= 0) || !(s->ramp_cycles > 0))
-        return fail(FVNA_E_INVALID, "need freq > 0, focal_length > 0, aperture >= 0, ramp_cycles > 0");
+    if (!(s->freq > 0) || !(s->focal_length > 0) || !(s->aperture >= 0))
+        return fail(FVNA_E_INVALID, "need freq > 0, focal_length > 0, aperture >= 0");
+    if (s->envelope == FVNA_ENV_RAMP) {
+        if (!(s->ramp_cycles > 0)) return fail(FVNA_E_INVALID, "the ramp envelope needs ramp_cycles > 0");
+    } else if (s->envelope == FVNA_ENV_PACKET) {
+        if (!(s->packet_cycles > 0)) return fail(FVNA_E_INVALID, "the packet envelope needs packet_cycles > 0");
+    } else {
+        return fail(FVNA_E_INVALID, "unknown source envelope");
+    }
     const fvna_params& p = c->p;
     c->d.sr_amp = s->p_surface / (p.rho0 * p.c0 * p.c0);
     c->d.sr_freq = s->freq * p.dx / p.c0;
     c->d.sr_F = s->focal_length / p.dx;
     c->d.sr_ap = s->aperture / p.dx;
-    c->d.sr_ramp = s->ramp_cycles;
-    // per-row table: focusing delay (reduced modulo one period) and direction cosines
-    std::vector<double> tab(3 * (size_t)p.ny);
+    c->d.sr_ramp = s->envelope == FVNA_ENV_RAMP ? s->ramp_cycles : 1.0;
+    c->d.sr_env = s->envelope;
+    c->d.sr_W = s->envelope == FVNA_ENV_PACKET ? s->packet_cycles : 1.0;
+    // per-row table: focusing delay reduced modulo one period, direction
+    // cosines, and the whole delay (for the packet envelope)
+    std::vector<double> tab(4 * (size_t)p.ny);
     const double f = c->d.sr_freq, F = c->d.sr_F;
     for (int j = 0; j < p.ny; ++j) {
         const double r = j + 0.5;
-        double ph = f * (r * r / (2.0 * F));
-        ph -= std::floor(ph);
+        const double delay = f * (r * r / (2.0 * F));
         const double h = std::sqrt(r * r + F * F);
-        tab[3 * (size_t)j] = ph;
-        tab[3 * (size_t)j + 1] = F / h;
-        tab[3 * (size_t)j + 2] = -r / h;
+        tab[4 * (size_t)j] = delay - std::floor(delay);
+        tab[4 * (size_t)j + 1] = F / h;
+        tab[4 * (size_t)j + 2] = -r / h;
+        tab[4 * (size_t)j + 3] = delay;
     }
     double* dtab = (double*)(c->scratch + OFF_SRCTAB);
     HIP_TRY(hipStreamSynchronize(c->stream));

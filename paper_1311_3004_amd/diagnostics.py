@@ -80,3 +80,34 @@ def compare(a, b):
     return {"p_plus_rel": abs(a["p_plus"] - b["p_plus"]) / abs(b["p_plus"]),
             "p_minus_rel": abs(a["p_minus"] - b["p_minus"]) / abs(b["p_minus"]),
             "harmonics_rel": [float(x) for x in h]}
+
+
+def axis_maxima(sim, t_end, probe_col=None, row=0, max_steps=10 ** 7):
+    """Advance `sim` one step at a time until its time reaches t_end and
+    return the largest pressure p' = c0^2 rho' seen at each cell of row `row`
+    (the cells next to the symmetry line: the on-axis pressure maxima of Sec.
+    4.2), and the time series (t, p) at column probe_col of that row."""
+    p = sim.params
+    c2 = p.c0 * p.c0
+    pmax = np.full(p.nx, -np.inf)
+    ts, ps = [], []
+    for _ in range(max_steps):
+        st = sim.fvna_get_stats()
+        if st["t"] >= t_end:
+            break
+        sim.fvna_step(1)
+        rp, _, _ = sim.fvna_get_window(0, row, p.nx, 1)
+        prow = rp[0] * c2
+        np.maximum(pmax, prow, out=pmax)
+        if probe_col is not None:
+            ts.append(sim.fvna_get_stats()["t"])
+            ps.append(prow[probe_col])
+    return pmax, np.array(ts), np.array(ps)
+
+
+def spectrum(t, p, freq, n=8):
+    """Amplitudes of harmonics 1..n of a transient p(t) sampled at times t
+    (nonuniform), by the trapezoidal Fourier integral over the whole record
+    scaled to amplitude units of a burst: |2/T int p e^{-2 pi i k f t} dt|
+    with T the record length."""
+    return harmonics(t, p, freq, n)

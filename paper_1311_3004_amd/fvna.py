@@ -52,7 +52,11 @@ class fvna_params(ctypes.Structure):
 class fvna_source(ctypes.Structure):
     _fields_ = [("freq", ctypes.c_double), ("p_surface", ctypes.c_double),
                 ("focal_length", ctypes.c_double), ("aperture", ctypes.c_double),
-                ("ramp_cycles", ctypes.c_double)]
+                ("ramp_cycles", ctypes.c_double), ("envelope", ctypes.c_int32),
+                ("packet_cycles", ctypes.c_double)]
+
+
+ENVELOPES = {"ramp": 0, "packet": 1}
 
 
 class fvna_stats(ctypes.Structure):
@@ -192,9 +196,11 @@ class Sim:
     def fvna_set_bc(self, side, bc):
         check(lib.fvna_set_bc(self.handle, int(side), BCS[bc] if isinstance(bc, str) else int(bc)))
 
-    def fvna_set_source(self, side, freq, p_surface, focal_length, aperture, ramp_cycles=3.0):
+    def fvna_set_source(self, side, freq, p_surface, focal_length, aperture, ramp_cycles=3.0,
+                        envelope="ramp", packet_cycles=4.0):
+        env = ENVELOPES[envelope] if isinstance(envelope, str) else int(envelope)
         s = fvna_source(float(freq), float(p_surface), float(focal_length), float(aperture),
-                        float(ramp_cycles))
+                        float(ramp_cycles), env, float(packet_cycles))
         check(lib.fvna_set_source(self.handle, int(side), ctypes.byref(s)))
 
     def fvna_set_taylor(self, amplitude_pa, x0_m, angle=0.0):
@@ -345,9 +351,12 @@ def sim_from_workload(w, device="cuda:0", precision=None, **over):
     if "source" in w:
         src = w["source"]
         s.fvna_set_source(0, src["freq"], src["p_surface"], src["focal_length"], src["aperture"],
-                          src.get("ramp_cycles", 3.0))
+                          src.get("ramp_cycles", 3.0), src.get("envelope", "ramp"),
+                          src.get("packet_cycles", 4.0))
     if "taylor" in w:
         t = w["taylor"]
         s.fvna_set_taylor(t["amplitude_pa"], t.get("x0_m", 0.0), t.get("angle", 0.0))
     s.fvna_set_state(*w["state"])
+    if w.get("t0", 0.0) != 0.0:
+        s.fvna_set_clock(w["t0"], 0.0)
     return s

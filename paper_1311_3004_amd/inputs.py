@@ -119,6 +119,38 @@ def c5_hifu_mixed(precision="f32_f16store"):
     return hifu_axisym(16384, 8192, 1e-5, 1e6, 40000, precision)
 
 
+# Soft tissue of the focused wave-packet experiment (Sec. 4.2): c0, rho0,
+# beta and the sound diffusivity delta, with the 1.1 MHz driving frequency.
+SOFT_TISSUE = {"c0": 1540.0, "rho0": 1000.0, "beta": 4.8, "delta": 6.4117e-4}
+PACKET_FREQ = 1.1e6
+
+
+def hifu_packet(eta=20, a=30.0, length_wl=60.0, margin_wl=10.0, cfl_target=0.9, precision="f64"):
+    """The focused wave-packet experiment of Sec. 4.2 on a fixed domain
+    (lengths in wavelengths, eta cells per wavelength): planar geometry, x1
+    along the propagation axis over length_wl, x2 transverse over a +
+    margin_wl with the symmetry line x2 = 0 reflecting; on x1 = 0 the source
+    of eq. hifuBC over 0 <= x2 <= a with focal length F = 50, amplitude
+    A = 4.217e-4 (1.00 MPa) and the packet envelope (half-width 4 periods);
+    zero-order extrapolation elsewhere.  The run starts at t0 = -6 periods,
+    where the packet is zero to machine precision, and ends when the packet
+    has crossed the domain (t_end)."""
+    med = dict(SOFT_TISSUE)
+    lam = med["c0"] / PACKET_FREQ
+    dx = lam / eta
+    nx = int(round(length_wl * eta))
+    ny = int(round((a + margin_wl) * eta))
+    z = np.zeros((ny, nx))
+    src = {"freq": PACKET_FREQ, "p_surface": 4.217e-4 * _p0(med), "focal_length": 50.0 * lam,
+           "aperture": a * lam, "envelope": "packet", "packet_cycles": 4.0}
+    t0 = -6.0 / PACKET_FREQ
+    t_end = (length_wl + 6.5) / PACKET_FREQ
+    return {"name": f"hifu-packet eta={eta} a={a:g} {nx}x{ny}", "nx": nx, "ny": ny, "dx": dx,
+            "medium": med, "bc": ("source", "extrap0", "reflect", "extrap0"), "geometry": "planar",
+            "precision": precision, "cfl_target": cfl_target, "cfl_max": 1.0, "source": src,
+            "t0": t0, "t_end": t_end, "wavelength": lam, "eta": eta, "state": (z, z.copy(), z.copy())}
+
+
 def c4_batch(n=64, seed=4, size_range=(256, 2048), steps=1000):
     """64 independent Cartesian simulations with seed-drawn uneven grids,
     amplitude U(0.1, 5) MPa, beta U(3, 5), delta log-uniform in [1e-6, 1e-5]

@@ -25,7 +25,8 @@ def run_oracle(orc, w, steps, fixed_dt=False, dt_si=0.0, **over):
     p = oracle_params(orc, w, fixed_dt=fixed_dt, **over)
     R, M, N = dimless_state(w)
     dt = dt_si * med["c0"] / w["dx"] if dt_si > 0 else 0.0
-    R1, M1, N1, info = orc.run(p, R, M, N, steps, dt=dt, want_hist=True)
+    t0 = w.get("t0", 0.0) * med["c0"] / w["dx"]
+    R1, M1, N1, info = orc.run(p, R, M, N, steps, t=t0, dt=dt, want_hist=True)
     return (R1, M1, N1), info
 
 

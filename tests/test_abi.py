@@ -76,3 +76,25 @@ def test_invalid_parameters_rejected(fv, over, msg):
         fv.workspace_size(p)
     assert e.value.status == fv.E_INVALID
     assert msg in str(e.value)
+
+
+def test_struct_layouts_match_the_header(fv, tmp_path):
+    """The ctypes mirrors of the ABI structs have the sizes and field offsets
+    the C compiler gives the header's structs."""
+    import subprocess
+    structs = {"fvna_params": fv.fvna_params, "fvna_source": fv.fvna_source, "fvna_stats": fv.fvna_stats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'  printf("{name} %zu\\n", sizeof({name}));')
+        for field, _ in cls._fields_:
+            lines.append(f'  printf("{name}.{field} %zu\\n", offsetof({name}, {field}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-o", str(exe), str(src)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.splitlines())
+    for name, cls in structs.items():
+        assert int(got[name]) == ctypes.sizeof(cls), name
+        for field, _ in cls._fields_:
+            assert int(got[f"{name}.{field}"]) == getattr(cls, field).offset, f"{name}.{field}"

@@ -117,6 +117,27 @@ def test_focused_source(orc, geometry):
     sim.fvna_destroy()
 
 
+def test_focused_packet_vs_oracle(orc):
+    """The focused wave packet of Sec. 4.2 (eq. hifuBC with the packet
+    envelope, run from t0 = -6 periods) on a small grid: 10 cells per
+    wavelength, aperture 5, 12 x 8 wavelengths, 200 adaptive steps (the packet
+    has crossed the domain)."""
+    from paper_1311_3004_amd import inputs
+    w = inputs.hifu_packet(eta=10, a=5.0, length_wl=12.0, margin_wl=3.0)
+    _say(f"case: {w['name']} adaptive from t0")
+    g, st, sim = run_gpu(w, 200, "f64")
+    o, info = run_oracle(orc, w, 200)
+    assert st["status"] == 0 and info["status"] == 0
+    med = w["medium"]
+    assert abs(st["t"] - info["t"] * w["dx"] / med["c0"]) <= 1e-12 * abs(st["t"]) + 1e-18
+    peak = np.max(np.abs(o[0]))
+    assert peak > 1e-5                       # the packet is in the domain
+    err = max_rel(g, o, peak=peak)
+    _say(f"  max rel err {err:.3e}")
+    assert err <= 1e-10
+    sim.fvna_destroy()
+
+
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 def test_tile_shape_invariance_bitwise(precision):
     w = pulse_workload(173, 141, ("extrap0", "reflect", "periodic", "periodic"), seed=5)
