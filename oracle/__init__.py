@@ -37,6 +37,7 @@ class Params(ctypes.Structure):
         ("src_focal", ctypes.c_double), ("src_aperture", ctypes.c_double),
         ("src_ramp_cycles", ctypes.c_double),
         ("src_envelope", ctypes.c_int), ("src_packet_cycles", ctypes.c_double),
+        ("src_stage2_on", ctypes.c_int), ("src_stage2", ctypes.c_double),
     ]
 
 
@@ -126,7 +127,8 @@ def make_params(nx, ny, beta, delta, bc=("extrap0",) * 4, geometry="planar",
     """Dimensionless parameters.  delta is delta~ = delta/(c0 dx).  taylor: dict
     amp, width, x0, y0, angle (cells).  source: dict amp, freq (cycles per
     dx/c0), focal, aperture (cells), ramp_cycles, envelope ("ramp" or
-    "packet"), packet_cycles."""
+    "packet"), packet_cycles, stage2 (time from which the whole side x- is
+    zero-order extrapolation; None: never)."""
     p = Params()
     p.nx, p.ny = int(nx), int(ny)
     p.beta, p.delta = float(beta), float(delta)
@@ -145,6 +147,9 @@ def make_params(nx, ny, beta, delta, bc=("extrap0",) * 4, geometry="planar",
     p.src_ramp_cycles = float(s.get("ramp_cycles", 3.0))
     p.src_envelope = {"ramp": 0, "packet": 1}[s.get("envelope", "ramp")]
     p.src_packet_cycles = float(s.get("packet_cycles", 4.0))
+    st2 = s.get("stage2")
+    p.src_stage2_on = int(st2 is not None)
+    p.src_stage2 = float(st2) if st2 is not None else 0.0
     return p
 
 
@@ -167,7 +172,9 @@ def make_params_si(nx, ny, dx, c0, rho0, beta, delta, bc=("extrap0",) * 4, geome
                   "focal": source_si["focal_length"] / dx, "aperture": source_si["aperture"] / dx,
                   "ramp_cycles": source_si.get("ramp_cycles", 3.0),
                   "envelope": source_si.get("envelope", "ramp"),
-                  "packet_cycles": source_si.get("packet_cycles", 4.0)}
+                  "packet_cycles": source_si.get("packet_cycles", 4.0),
+                  "stage2": (None if source_si.get("stage2_time") is None
+                             else source_si["stage2_time"] * c0 / dx)}
     return make_params(nx, ny, beta, delta / (c0 * dx), bc, geometry, cfl_target, cfl_max,
                        max_retries, fixed_dt, taylor, source)
 

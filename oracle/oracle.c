@@ -57,6 +57,9 @@ typedef struct {
     int src_envelope;         /* 0: sin^2 ramp over src_ramp_cycles periods from t = 0;
                                  1: the packet of eq. hifuBC:g, width src_packet_cycles */
     double src_packet_cycles;
+    int src_stage2_on;        /* 1: from t >= src_stage2 on, the whole side x- is zero-order
+                                 extrapolation (second stage of Sec. 4.2); 0: never */
+    double src_stage2;
 } orc_params;
 
 typedef struct {
@@ -336,7 +339,8 @@ static void set_ghost(const orc_params *p, double t, field_t *g, int side, int g
     }
     if (bc == BC_SOURCE) {   /* valid on side x- only (checked at entry) */
         double r = y;
-        if (r <= p->src_aperture) {
+        int first_stage = !(p->src_stage2_on && t >= p->src_stage2);
+        if (first_stage && r <= p->src_aperture) {
             double gg = source_g(p, r, t);
             double h = sqrt(r * r + p->src_focal * p->src_focal);
             g->R[d] = gg;
@@ -547,6 +551,7 @@ static int check_params(const orc_params *p)
     if ((p->bc[2] == BC_PERIODIC) != (p->bc[3] == BC_PERIODIC)) return ORC_E_INVALID;
     if (p->src_envelope < 0 || p->src_envelope > 1) return ORC_E_INVALID;
     if (p->src_envelope == 1 && !(p->src_packet_cycles > 0.0)) return ORC_E_INVALID;
+    if (p->src_stage2_on != 0 && (p->src_stage2_on != 1 || !isfinite(p->src_stage2))) return ORC_E_INVALID;
     return ORC_OK;
 }
 

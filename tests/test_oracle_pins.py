@@ -295,7 +295,7 @@ def test_taylor_shock_table1_band(orc):
     """Table 1, theta_T = 0: E1 convergence rates 1.63..2.00 and E1 at the
     finest mesh 2.36e-5 (best) .. 2.91e-4 (worst); nu std below 1e-8.
     The mesh parameter is read as cells per 10%-90% rise of the step, which is
-    2.197 tanh units (reading A8), so the paper's eta = 82 is 37.3 cells per
+    2.197 tanh units, the paper's eta read as cells per 10-90% rise, so the paper's eta = 82 is 37.3 cells per
     tanh unit here; E1 there is extrapolated from eta = 5, 10, 20 with the
     measured rate and must fall inside the printed band (factor 2 margin)."""
     etas = [5, 10, 20]
@@ -521,7 +521,7 @@ def test_travelling_speed_matches_rankine_hugoniot():
     assert abs(V * ML - (flux_mom(ML, uL, RL) - flux_mom(0.0, 0.0, RR))) < 1e-15
 
 
-# -- Focused source with the packet envelope (eq. hifuBC, reading A10) ----------
+# -- Focused source with the packet envelope (eq. hifuBC:g) -------------------
 
 def test_packet_source_launches_the_packet_as_a_plane_wave(orc):
     """With an unfocused source covering the whole side (F -> inf, aperture
@@ -558,3 +558,37 @@ def test_packet_source_launches_the_packet_as_a_plane_wave(orc):
     assert np.max(np.abs(ms - rs)) <= 0.03 * A
     assert np.max(np.abs(ns)) <= 1e-3 * A
     assert abs(np.max(np.abs(rs)) / A - 1.0) < 0.03      # flat top at full amplitude
+
+
+def test_second_stage_turns_the_source_side_into_extrapolation(orc):
+    """Sec. 4.2 runs the packet in two stages: the source on 0 <= x2 <= a and
+    extrapolation beyond it, then zero-order extrapolation over the whole
+    border x1 = 0.  A run that crosses the switch time must equal, bit for
+    bit, a run with the source up to the first step whose t_n reaches it,
+    continued from that state with an extrapolating side x- (boundary data at
+    t_n).  A switch tested on t_{n+1}, a switch that keeps the source rows,
+    or one that never happens fails this; so does the switch leaving the
+    first stage unchanged (compared with a run with no second stage)."""
+    eta, W, A = 20.0, 4.0, 2e-4
+    f = 1.0 / eta
+    src = {"amp": A, "freq": f, "focal": 50.0 * eta, "aperture": 10.5, "envelope": "packet",
+           "packet_cycles": W}
+    bc = ("source", "extrap0", "reflect", "extrap0")
+    t0, dt, n1, n2 = -6.0 / f, 0.9, 120, 60
+    t_switch = t0 + (n1 - 0.5) * dt          # between t_{n1-1} and t_{n1}
+    mk = lambda b, stage2: orc.make_params(90, 24, 4.8, 1e-3, bc=b, fixed_dt=True,
+                                           source=dict(src, stage2=stage2))
+    Z = np.zeros((24, 90))
+    R1, M1, N1, i1 = orc.run(mk(bc, None), Z, Z, Z, n1, t=t0, dt=dt)
+    R0, M0, N0, i0 = orc.run(mk(bc, t_switch), Z, Z, Z, n1, t=t0, dt=dt)
+    assert i1["status"] == 0 and i0["status"] == 0
+    for a, b in ((R1, R0), (M1, M0), (N1, N0)):
+        assert np.array_equal(a, b)
+    assert np.max(np.abs(R1)) > 0.3 * A              # the packet has entered
+    R2, M2, N2, i2 = orc.run(mk(("extrap0",) + bc[1:], None), R1, M1, N1, n2, t=i1["t"], dt=dt)
+    Rs, Ms, Ns, i3 = orc.run(mk(bc, t_switch), Z, Z, Z, n1 + n2, t=t0, dt=dt)
+    Rk, Mk, Nk, _ = orc.run(mk(bc, None), R1, M1, N1, n2, t=i1["t"], dt=dt)
+    assert i2["status"] == 0 and i3["status"] == 0
+    for a, b in ((R2, Rs), (M2, Ms), (N2, Ns)):
+        assert np.array_equal(a, b)
+    assert np.max(np.abs(Rk - Rs)) > 1e-3 * A         # the switch changed something
