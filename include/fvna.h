@@ -102,7 +102,8 @@ typedef struct {
 } fvna_params;
 
 /* Focused boundary source of eq. hifuBC on side x-: for the ghost rows whose
- * centre r (distance from side y-) is <= aperture,
+ * centre r (distance from side y-) is <= aperture (all other rows of the side
+ * are zero-order extrapolation),
  *   R = g, M = F g / sqrt(r^2 + F^2), N = -r g / sqrt(r^2 + F^2),
  *   g = (p_surface / (rho0 c0^2)) w sin(2 pi freq tau),  tau = t + r^2 / (2 F c0),
  * with the envelope w chosen by `envelope`:
@@ -114,6 +115,9 @@ typedef struct {
  *                    half-width packet_cycles periods centred on tau = 0; the
  *                    paper uses 4 and starts the run at a negative time, see
  *                    fvna_set_clock). */
+/* With second_stage = 1 the run has the two stages of Sec. 4.2: from the
+ * first step whose start time t_n is >= stage2_time on, the whole side x- is
+ * zero-order extrapolation (the source rows included). */
 typedef enum { FVNA_ENV_RAMP = 0, FVNA_ENV_PACKET = 1 } fvna_envelope;
 typedef struct {
     double freq;               /* [Hz] > 0 */
@@ -123,6 +127,8 @@ typedef struct {
     double ramp_cycles;        /* > 0 (FVNA_ENV_RAMP) */
     int32_t envelope;          /* fvna_envelope */
     double packet_cycles;      /* > 0 (FVNA_ENV_PACKET) */
+    int32_t second_stage;      /* 0: the source stays on; 1: switch at stage2_time */
+    double stage2_time;        /* [s], finite (second_stage = 1) */
 } fvna_source;
 
 typedef struct {

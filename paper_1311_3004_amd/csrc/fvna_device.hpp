@@ -87,6 +87,7 @@ struct SimDesc {
     const double* src_tab;       // focused source, per row j: frac(f r^2/(2F)), F/h, -r/h, f r^2/(2F) (null: none)
     int sr_env;                  // 0: sin^2 ramp in t; 1: packet exp(-(f tau / sr_W)^10)
     double sr_W;                 // packet half-width in periods
+    double sr_t2;                // start of the second stage (+inf: none)
 };
 
 // ---------------------------------------------------------------------------
@@ -401,8 +402,10 @@ __device__ __forceinline__ void taylor_at(const SimDesc& d, double x, double y, 
 // period, and the direction cosines F/h, -r/h with h = sqrt(r^2 + F^2) --
 // come from a table filled when the source is set.  The sine's phase is the
 // sum of the reduced parts reduced again, in FP64; the packet envelope of eq.
-// hifuBC:g, exp(-(f tau / W)^10), takes the whole f tau.
-struct SourceClock { double ft_frac, ft, env; };
+// hifuBC:g, exp(-(f tau / W)^10), takes the whole f tau.  `ap` is the
+// aperture in cells during the first stage and -1 (no source row) in the
+// second, when the whole side is zero-order extrapolation (Sec. 4.2).
+struct SourceClock { double ft_frac, ft, env, ap; };
 
 __device__ __forceinline__ SourceClock source_clock(const SimDesc& d, double t)
 {
@@ -418,6 +421,7 @@ __device__ __forceinline__ SourceClock source_clock(const SimDesc& d, double t)
     }
     c.ft = f * t;
     c.ft_frac = c.ft - floor(c.ft);
+    c.ap = t < d.sr_t2 ? d.sr_ap : -1.0;
     return c;
 }
 
@@ -591,7 +595,7 @@ __device__ __forceinline__ void march(const SimDesc& d, int strip, int seg)
     const T hdt = T(0.5) * dt;
     const float sc0 = d.scale[0], sc1 = d.scale[1], sc2 = d.scale[2];
     const float is0 = d.inv_scale[0], is1 = d.inv_scale[1], is2 = d.inv_scale[2];
-    SourceClock src_clk = {0.0, 0.0, 0.0};       // focused source at this step's time
+    SourceClock src_clk = {0.0, 0.0, 0.0, -1.0}; // focused source at this step's time
     if (EDGE && d.bc[0] == BC_SOURCE) src_clk = source_clock(d, tn);
 
     // ---- where this lane's Q^n comes from (x boundary rule) ----
@@ -671,7 +675,7 @@ __device__ __forceinline__ void march(const SimDesc& d, int strip, int seg)
                 taylor_at(d, col + 0.5, vr + 0.5, tn, R, M, N);
                 q.R = (T)R; q.M = (T)M; q.N = (T)N;
             } else if (xkind == 2) {
-                if (vr + 0.5 <= d.sr_ap) source_at<T>(d, vr, src_clk, q.R, q.M, q.N);
+                if (vr + 0.5 <= src_clk.ap) source_at<T>(d, vr, src_clk, q.R, q.M, q.N);
             }
         }
         const T irho = rcp(T(1) + q.R);
@@ -754,7 +758,7 @@ __device__ __forceinline__ void march(const SimDesc& d, int strip, int seg)
                     const int b = d.bc[0];
                     if (b == BC_REFLECT) { uxl = -in.us; vxl = in.vs; }
                     else if (b == BC_TAYLOR) taylor_uv(-0.5, j + 0.5, uxl, vxl);
-                    else if (b == BC_SOURCE && j + 0.5 <= d.sr_ap) {
+                    else if (b == BC_SOURCE && j + 0.5 <= src_clk.ap) {
                         T R, M, N;
                         source_at<T>(d, j, src_clk, R, M, N);
                         const T ir = rcp(T(1) + R);

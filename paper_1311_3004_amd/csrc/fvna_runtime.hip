@@ -170,10 +170,13 @@ __device__ Cell<T> cell_at(const SimDesc& d, int i, int j, double t)
             taylor_at(d, i + 0.5, j + 0.5, t, R, M, N);
             return Cell<T>{(T)R, (T)M, (T)N};
         }
-        if (b == BC_SOURCE && (j + 0.5) <= d.sr_ap) {
-            Cell<T> q;
-            source_at<T>(d, j, source_clock(d, t), q.R, q.M, q.N);
-            return q;
+        if (b == BC_SOURCE) {
+            const SourceClock sc = source_clock(d, t);
+            if ((j + 0.5) <= sc.ap) {
+                Cell<T> q;
+                source_at<T>(d, j, sc, q.R, q.M, q.N);
+                return q;
+            }
         }
         if (b == BC_PERIODIC) {
             if (side == 0) si = i + nx;
@@ -534,7 +537,7 @@ static void fill_desc(SimDesc& d, const fvna_params* p, void* a, void* b, Clock*
     d.cfl_target = p->cfl_target;
     d.cfl_max = p->cfl_max;
     d.ta_amp = 0.0; d.ta_w = 1.0; d.ta_cos = 1.0; d.ta_sin = 0.0;
-    d.sr_freq = 1.0; d.sr_F = 1e30; d.sr_ramp = 3.0;
+    d.sr_freq = 1.0; d.sr_F = 1e30; d.sr_ramp = 3.0; d.sr_t2 = INFINITY;
     for (int f = 0; f < 3; ++f) {
         const bool half = p->precision == FVNA_F32_F16STORE || p->precision == FVNA_F32_BF16STORE;
         const double sc = (half && p->store_scale[f] > 0.0) ? p->store_scale[f] : 1.0;
@@ -707,6 +710,8 @@ fvna_status fvna_set_source(fvna_ctx* c, int32_t side, const fvna_source* s)
     } else {
         return fail(FVNA_E_INVALID, "unknown source envelope");
     }
+    if (s->second_stage != 0 && (s->second_stage != 1 || !std::isfinite(s->stage2_time)))
+        return fail(FVNA_E_INVALID, "second_stage must be 0 or 1, with a finite stage2_time");
     const fvna_params& p = c->p;
     c->d.sr_amp = s->p_surface / (p.rho0 * p.c0 * p.c0);
     c->d.sr_freq = s->freq * p.dx / p.c0;
@@ -715,6 +720,7 @@ fvna_status fvna_set_source(fvna_ctx* c, int32_t side, const fvna_source* s)
     c->d.sr_ramp = s->envelope == FVNA_ENV_RAMP ? s->ramp_cycles : 1.0;
     c->d.sr_env = s->envelope;
     c->d.sr_W = s->envelope == FVNA_ENV_PACKET ? s->packet_cycles : 1.0;
+    c->d.sr_t2 = s->second_stage ? s->stage2_time * p.c0 / p.dx : INFINITY;
     // per-row table: focusing delay reduced modulo one period, direction
     // cosines, and the whole delay (for the packet envelope)
     std::vector<double> tab(4 * (size_t)p.ny);

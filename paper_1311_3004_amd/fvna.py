@@ -53,7 +53,8 @@ class fvna_source(ctypes.Structure):
     _fields_ = [("freq", ctypes.c_double), ("p_surface", ctypes.c_double),
                 ("focal_length", ctypes.c_double), ("aperture", ctypes.c_double),
                 ("ramp_cycles", ctypes.c_double), ("envelope", ctypes.c_int32),
-                ("packet_cycles", ctypes.c_double)]
+                ("packet_cycles", ctypes.c_double), ("second_stage", ctypes.c_int32),
+                ("stage2_time", ctypes.c_double)]
 
 
 ENVELOPES = {"ramp": 0, "packet": 1}
@@ -197,10 +198,13 @@ class Sim:
         check(lib.fvna_set_bc(self.handle, int(side), BCS[bc] if isinstance(bc, str) else int(bc)))
 
     def fvna_set_source(self, side, freq, p_surface, focal_length, aperture, ramp_cycles=3.0,
-                        envelope="ramp", packet_cycles=4.0):
+                        envelope="ramp", packet_cycles=4.0, stage2_time=None):
+        """stage2_time None: the source stays on; else the time [s] from which
+        the whole side is zero-order extrapolation."""
         env = ENVELOPES[envelope] if isinstance(envelope, str) else int(envelope)
         s = fvna_source(float(freq), float(p_surface), float(focal_length), float(aperture),
-                        float(ramp_cycles), env, float(packet_cycles))
+                        float(ramp_cycles), env, float(packet_cycles), int(stage2_time is not None),
+                        float(stage2_time) if stage2_time is not None else 0.0)
         check(lib.fvna_set_source(self.handle, int(side), ctypes.byref(s)))
 
     def fvna_set_taylor(self, amplitude_pa, x0_m, angle=0.0):
@@ -352,7 +356,7 @@ def sim_from_workload(w, device="cuda:0", precision=None, **over):
         src = w["source"]
         s.fvna_set_source(0, src["freq"], src["p_surface"], src["focal_length"], src["aperture"],
                           src.get("ramp_cycles", 3.0), src.get("envelope", "ramp"),
-                          src.get("packet_cycles", 4.0))
+                          src.get("packet_cycles", 4.0), src.get("stage2_time"))
     if "taylor" in w:
         t = w["taylor"]
         s.fvna_set_taylor(t["amplitude_pa"], t.get("x0_m", 0.0), t.get("angle", 0.0))

@@ -133,8 +133,9 @@ def hifu_packet(eta=20, a=30.0, length_wl=60.0, margin_wl=10.0, cfl_target=0.9, 
     of eq. hifuBC over 0 <= x2 <= a with focal length F = 50, amplitude
     A = 4.217e-4 (1.00 MPa) and the packet envelope (half-width 4 periods);
     zero-order extrapolation elsewhere.  The run starts at t0 = -6 periods,
-    where the packet is zero to machine precision, and ends when the packet
-    has crossed the domain (t_end)."""
+    where the envelope is 9e-26, and ends when the packet has crossed the
+    domain (t_end).  At t = +6 periods, when the packet has left the source,
+    the second stage begins: the whole border x1 = 0 is extrapolating."""
     med = dict(SOFT_TISSUE)
     lam = med["c0"] / PACKET_FREQ
     dx = lam / eta
@@ -142,7 +143,8 @@ def hifu_packet(eta=20, a=30.0, length_wl=60.0, margin_wl=10.0, cfl_target=0.9, 
     ny = int(round((a + margin_wl) * eta))
     z = np.zeros((ny, nx))
     src = {"freq": PACKET_FREQ, "p_surface": 4.217e-4 * _p0(med), "focal_length": 50.0 * lam,
-           "aperture": a * lam, "envelope": "packet", "packet_cycles": 4.0}
+           "aperture": a * lam, "envelope": "packet", "packet_cycles": 4.0,
+           "stage2_time": 6.0 / PACKET_FREQ}
     t0 = -6.0 / PACKET_FREQ
     t_end = (length_wl + 6.5) / PACKET_FREQ
     return {"name": f"hifu-packet eta={eta} a={a:g} {nx}x{ny}", "nx": nx, "ny": ny, "dx": dx,

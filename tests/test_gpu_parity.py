@@ -121,20 +121,31 @@ def test_focused_packet_vs_oracle(orc):
     """The focused wave packet of Sec. 4.2 (eq. hifuBC with the packet
     envelope, run from t0 = -6 periods) on a small grid: 10 cells per
     wavelength, aperture 5, 12 x 8 wavelengths, 200 adaptive steps (the packet
-    has crossed the domain)."""
-    from paper_1311_3004_amd import inputs
+    has crossed the domain).  The run passes the start of the second stage
+    (t = +6 periods, the whole side x- extrapolating); the oracle run without
+    it must differ from both, so the switch is exercised."""
+    from paper_1311_3004_amd import fvna, inputs
     w = inputs.hifu_packet(eta=10, a=5.0, length_wl=12.0, margin_wl=3.0)
-    _say(f"case: {w['name']} adaptive from t0")
+    _say(f"case: {w['name']} adaptive from t0, second stage")
     g, st, sim = run_gpu(w, 200, "f64")
     o, info = run_oracle(orc, w, 200)
     assert st["status"] == 0 and info["status"] == 0
     med = w["medium"]
+    assert st["t"] > w["source"]["stage2_time"] + 2.0 / inputs.PACKET_FREQ
     assert abs(st["t"] - info["t"] * w["dx"] / med["c0"]) <= 1e-12 * abs(st["t"]) + 1e-18
     peak = np.max(np.abs(o[0]))
     assert peak > 1e-5                       # the packet is in the domain
     err = max_rel(g, o, peak=peak)
     _say(f"  max rel err {err:.3e}")
     assert err <= 1e-10
+    w1 = dict(w, source=dict(w["source"], stage2_time=None))
+    o1, _ = run_oracle(orc, w1, 200)
+    assert max_rel(o1, o, peak=peak) > 1e-6
+    for bad in (dict(stage2_time=float("nan")), dict(stage2_time=float("inf"))):
+        src = dict(w["source"], **bad)
+        with pytest.raises(fvna.FvnaError):
+            sim.fvna_set_source(0, src["freq"], src["p_surface"], src["focal_length"],
+                                src["aperture"], envelope="packet", stage2_time=src["stage2_time"])
     sim.fvna_destroy()
 
 
