@@ -220,3 +220,40 @@ def source_g(p, r, t):
 
 __all__ = ["build", "lib", "roe", "mc", "flux", "make_params", "make_params_si", "run",
            "dry_smax", "taylor_value", "source_g", "BC", "GEOM", "Params", "Stats"]
+
+
+def shift(R, M, N, ncols):
+    """Move the domain ncols cells along +x1 (the moving domain of Sec. 4):
+    column i of the result is column i + ncols of the input; the ncols columns
+    that enter on the right hold undisturbed medium (R = M = N = 0)."""
+    out = []
+    for F in (R, M, N):
+        G = np.zeros_like(F)
+        if ncols < F.shape[1]:
+            G[:, : F.shape[1] - ncols] = F[:, ncols:]
+        out.append(G)
+    return out[0], out[1], out[2]
+
+
+def run_window(p, R, M, N, nsteps, t, dt, t1, check_every, quantum, x_off=0):
+    """The two stages of Sec. 4 on a moving domain.  Steps are taken in
+    chunks of check_every accepted steps; after each chunk, once t >= t1 (the
+    packet centre has reached the middle of the domain), the domain origin is
+    moved to quantum * floor((t - t1) / quantum) cells (the domain follows
+    the packet at the speed c0 = 1 cell per unit time, in jumps of quantum
+    cells).  Returns (R, M, N, info, x_off)."""
+    done = 0
+    info = None
+    while done < nsteps:
+        k = min(check_every, nsteps - done)
+        R, M, N, info = run(p, R, M, N, k, t=t, dt=dt)
+        if info["status"] != OK:
+            return R, M, N, info, x_off
+        t, dt = info["t"], info["dt_next"]
+        done += k
+        if k == check_every and t >= t1:
+            target = quantum * int(np.floor((t - t1) / quantum))
+            if target > x_off:
+                R, M, N = shift(R, M, N, target - x_off)
+                x_off = target
+    return R, M, N, info, x_off

@@ -592,3 +592,54 @@ def test_second_stage_turns_the_source_side_into_extrapolation(orc):
     for a, b in ((R2, Rs), (M2, Ms), (N2, Ns)):
         assert np.array_equal(a, b)
     assert np.max(np.abs(Rk - Rs)) > 1e-3 * A         # the switch changed something
+
+
+# -- Moving domain (Sec. 4: two stages, the domain follows the packet) ----------
+
+def test_shift_moves_columns_and_fills_undisturbed_medium(orc):
+    """Definition of one move of the domain by k cells along +x1."""
+    rng = np.random.default_rng(11)
+    R, M, N = (rng.standard_normal((3, 7)) for _ in range(3))
+    for k in (0, 1, 4, 7, 9):
+        R2, M2, N2 = orc.shift(R, M, N, k)
+        for a, b in ((R, R2), (M, M2), (N, N2)):
+            for i in range(7):
+                want = a[:, i + k] if i + k < 7 else np.zeros(3)
+                assert np.array_equal(b[:, i], want)
+
+
+def test_moving_domain_matches_the_fixed_domain_inside_the_window(orc):
+    """A focused packet (eq. hifuBC, packet envelope) run 30 periods on a
+    moving domain 20 wavelengths long -- still until the packet centre
+    reaches the middle of the domain at t1, then following it in jumps of 8
+    cells checked every 8 steps, the source side extrapolating from t1 on --
+    must equal, column for column at its current origin, the same run on a
+    fixed domain 36 wavelengths long, except within 4 wavelengths of the
+    trailing edge, whose extrapolated data differ from the cut-off state (the
+    difference dies out within a few cells, so the rest agrees to rounding).
+    A move in the wrong direction, by the wrong amount, at the wrong time or
+    with anything but undisturbed medium entering on the right fails this."""
+    eta, A, F, a = 8.0, 3e-4, 20.0, 4.0
+    f = 1.0 / eta
+    ny = int((a + 3) * eta)
+    nxw, nxf = int(20 * eta), int(36 * eta)
+    t0, t1 = -6.0 / f, 10.0 / f
+
+    def params(nx):
+        return orc.make_params(nx, ny, 4.8, 3e-4 * eta, bc=("source", "extrap0", "reflect", "extrap0"),
+                               source={"amp": A, "freq": f, "focal": F * eta, "aperture": a * eta,
+                                       "envelope": "packet", "packet_cycles": 4.0, "stage2": t1})
+    steps = 266
+    Rf, Mf, Nf, i_f = orc.run(params(nxf), np.zeros((ny, nxf)), np.zeros((ny, nxf)),
+                              np.zeros((ny, nxf)), steps, t=t0)
+    Z = np.zeros((ny, nxw))
+    Rw, Mw, Nw, i_w, x_off = orc.run_window(params(nxw), Z, Z, Z, steps, t0, 0.0, t1, 8, 8)
+    assert i_f["status"] == 0 and i_w["status"] == 0
+    assert i_w["t"] == i_f["t"]
+    assert x_off % 8 == 0 and 96 <= x_off <= i_w["t"] - t1   # moved >= 12 wavelengths, never ahead
+    peak = np.max(np.abs(Rf))
+    keep = slice(int(4 * eta), nxw)
+    for w_, f_ in ((Rw, Rf), (Mw, Mf), (Nw, Nf)):
+        ref = f_[:, x_off:x_off + nxw]
+        assert np.max(np.abs(w_[:, keep] - ref[:, keep])) <= 1e-13 * peak
+    assert np.max(np.abs(Rf[:, x_off:x_off + nxw])) >= 0.99 * peak   # the packet is inside
