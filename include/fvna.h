@@ -189,6 +189,41 @@ fvna_status fvna_step(fvna_ctx* c, int64_t nsteps);
  * the latched device status. */
 fvna_status fvna_sync(fvna_ctx* c);
 
+/* Move the domain ncols cells along +x1 (the moving domain of Sec. 4):
+ * afterwards column i holds what column i + ncols held, and the ncols columns
+ * that enter on the right hold undisturbed medium (zero perturbation).  The
+ * stored values are copied as they are (exact in every precision).  Time, time
+ * step and statistics are unchanged; side data stay attached to the domain
+ * (the source stays at its left edge), so both x sides must be EXTRAP0,
+ * REFLECT or SOURCE.  0 <= ncols <= nx; 0 does nothing.  Asynchronous on the
+ * stream; FVNA_E_INVALID for a bad argument. */
+fvna_status fvna_shift(fvna_ctx* c, int32_t ncols);
+
+/* The two stages of Sec. 4 on a moving domain: the domain stays still until
+ * the packet centre, travelling at c0, reaches its middle at t1; from then on
+ * it follows the packet.  The paper gives no rule for the moves; here the
+ * state is checked after every check_every-th accepted step (counted across
+ * calls by `phase`), and once t >= t1 the origin moves to
+ * quantum * floor((t - t1) c0 / (dx quantum)) cells from the start (fvna_shift
+ * by the difference, at most nx).  The source's second stage (fvna_source
+ * .stage2_time, normally t1) is set separately. */
+typedef struct {
+    double t1;                 /* [s], finite */
+    int32_t check_every;       /* >= 1 */
+    int32_t quantum;           /* cells, >= 1 */
+} fvna_window;
+typedef struct {
+    int64_t x_off;             /* cells the domain has moved (start at 0) */
+    int64_t phase;             /* accepted steps since the last check, in [0, check_every) */
+} fvna_window_state;
+
+/* Advance nsteps accepted steps with the moving-domain rule above, updating
+ * *st.  Synchronises the stream at every check (once per check_every steps)
+ * and returns the first device status that is not FVNA_OK (the steps of the
+ * failing chunk are not all taken).  FVNA_E_INVALID for bad arguments or x
+ * sides that cannot move (as fvna_shift). */
+fvna_status fvna_step_window(fvna_ctx* c, const fvna_window* w, fvna_window_state* st, int64_t nsteps);
+
 /* Synchronise and copy the current state out (same units and layout as set_state). */
 fvna_status fvna_get_state(fvna_ctx* c, double* rho_p, double* mom_x, double* mom_y);
 

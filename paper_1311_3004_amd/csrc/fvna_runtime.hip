@@ -284,6 +284,36 @@ __global__ void k_export(SimDesc d, double* __restrict__ dst, int field, int row
     dst[(size_t)r * ncols + i] = (double)Codec<S, T>::ld(src[i], d.scale[field]) * factor;
 }
 
+// Moving domain (Sec. 4): the current state moved `ncols` cells along +x1 into
+// the other buffer, undisturbed medium (stored zero, whatever the scale)
+// entering on the right and in the row padding.  Raw copies of the stored
+// values: no conversion, so a move is exact in every precision.  k_flip then
+// makes the moved state current; it runs after every block of k_shift has
+// read `cur`.
+template <typename S>
+__global__ __launch_bounds__(256) void k_shift(SimDesc d, int ncols)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= d.pitch) return;
+    const int cur = d.clk->cur;
+    const S* __restrict__ src = (const S*)d.buf[cur];
+    S* __restrict__ dst = (S*)d.buf[cur ^ 1];
+    const bool inside = i < d.nx - ncols;
+    for (int r = blockIdx.y; r < 3 * d.ny; r += gridDim.y) {
+        const int field = r / d.ny, row = r - field * d.ny;
+        const size_t base = (size_t)field * d.plane + (size_t)row * d.pitch;
+        S v;
+        if (inside) v = src[base + i + ncols];
+        else __builtin_memset(&v, 0, sizeof(S));
+        dst[base + i] = v;
+    }
+}
+
+__global__ void k_flip(Clock* c)
+{
+    if (threadIdx.x == 0) c->cur ^= 1;
+}
+
 // Fixed-order FP64 sums: block b sums rows b, b + NB, ... with a fixed
 // thread stride and a fixed tree; the final pass sums the NB partials.
 constexpr int SUM_BLOCKS = 512;
@@ -472,6 +502,7 @@ struct Launcher {
     void (*imp)(const SimDesc&, const double*, int, int, int, double, int, hipStream_t);
     void (*exp)(const SimDesc&, double*, int, int, int, int, int, double, hipStream_t);
     void (*sums)(const SimDesc&, double*, hipStream_t);
+    void (*shift)(const SimDesc&, int, hipStream_t);
 };
 
 template <typename S, typename T, int AXI>
@@ -503,6 +534,11 @@ Launcher make_launcher()
     L.sums = [](const SimDesc& d, double* part, hipStream_t s) {
         hipLaunchKernelGGL((k_sums_partial<S, T>), dim3(SUM_BLOCKS), dim3(256), 0, s, d, part);
         hipLaunchKernelGGL(k_sums_final, dim3(1), dim3(256), 0, s, part, part + SUM_BLOCKS * 3);
+    };
+    L.shift = [](const SimDesc& d, int ncols, hipStream_t s) {
+        const int rows = std::min(3 * d.ny, 65535);
+        hipLaunchKernelGGL(k_shift<S>, dim3((d.pitch + 255) / 256, rows), dim3(256), 0, s, d, ncols);
+        hipLaunchKernelGGL(k_flip, dim3(1), dim3(64), 0, s, d.clk);
     };
     return L;
 }
@@ -829,6 +865,60 @@ fvna_status fvna_sync(fvna_ctx* c)
         if (s) return s;
     }
     return fail(FVNA_E_STATE, "steps still owed after many top-up rounds");
+}
+
+fvna_status fvna_shift(fvna_ctx* c, int32_t ncols)
+{
+    if (!c) return fail(FVNA_E_INVALID, "ctx is NULL");
+    if (ncols < 0 || ncols > c->p.nx) return fail(FVNA_E_INVALID, "ncols must be in [0, nx]");
+    for (int side = 0; side < 2; ++side) {
+        const int b = c->p.bc[side];
+        if (b == FVNA_BC_PERIODIC || b == FVNA_BC_TAYLOR)
+            return fail(FVNA_E_INVALID, "moving the domain needs EXTRAP0, REFLECT or SOURCE x sides");
+    }
+    if (ncols == 0) return FVNA_OK;
+    c->L.shift(c->d, ncols, c->stream);
+    HIP_TRY(hipGetLastError());
+    return FVNA_OK;
+}
+
+fvna_status fvna_step_window(fvna_ctx* c, const fvna_window* w, fvna_window_state* st, int64_t nsteps)
+{
+    if (!c || !w || !st) return fail(FVNA_E_INVALID, "NULL argument");
+    if (nsteps < 0) return fail(FVNA_E_INVALID, "nsteps must be >= 0");
+    if (w->check_every < 1 || w->quantum < 1 || !std::isfinite(w->t1))
+        return fail(FVNA_E_INVALID, "need check_every >= 1, quantum >= 1 and a finite t1");
+    if (st->x_off < 0 || st->phase < 0 || st->phase >= w->check_every)
+        return fail(FVNA_E_INVALID, "window state out of range");
+    for (int side = 0; side < 2; ++side) {
+        const int b = c->p.bc[side];
+        if (b == FVNA_BC_PERIODIC || b == FVNA_BC_TAYLOR)
+            return fail(FVNA_E_INVALID, "moving the domain needs EXTRAP0, REFLECT or SOURCE x sides");
+    }
+    const fvna_params& p = c->p;
+    const double t1 = w->t1 * p.c0 / p.dx;        // cells travelled at c0 per unit time
+    while (nsteps > 0) {
+        const int64_t k = std::min<int64_t>(nsteps, w->check_every - st->phase);
+        fvna_status s = fvna_step(c, k);
+        if (s) return s;
+        s = fvna_sync(c);
+        if (s) return s;
+        nsteps -= k;
+        st->phase += k;
+        if (st->phase < w->check_every) continue;
+        st->phase = 0;
+        Clock h;
+        s = read_clock(c, &h);
+        if (s) return s;
+        if (!(h.t >= t1)) continue;
+        const int64_t target = (int64_t)w->quantum * (int64_t)std::floor((h.t - t1) / w->quantum);
+        if (target <= st->x_off) continue;
+        const int64_t move = std::min<int64_t>(target - st->x_off, p.nx);
+        c->L.shift(c->d, (int)move, c->stream);
+        HIP_TRY(hipGetLastError());
+        st->x_off = target;
+    }
+    return FVNA_OK;
 }
 
 // Copy a window of the current state of a context out (no synchronisation of

@@ -82,32 +82,59 @@ def compare(a, b):
             "harmonics_rel": [float(x) for x in h]}
 
 
-def axis_maxima(sim, t_end, probe_col=None, row=0, max_steps=10 ** 7):
+def axis_maxima(sim, t_end, probe_col=None, row=0, max_steps=10 ** 7, window=None, path_cells=None):
     """Advance `sim` one step at a time until its time reaches t_end and
     return the largest pressure p' = c0^2 rho' seen at each cell of row `row`
     (the cells next to the symmetry line: the on-axis pressure maxima of Sec.
-    4.2), and the time series (t, p) at column probe_col of that row."""
+    4.2), and the time series (t, p) at column probe_col of that row.
+
+    window: a dict t1, check_every, quantum -- the domain moves (fvna_step_window)
+    and the maxima are kept over path_cells columns of the path it covers
+    (column x_off + i of the path is column i of the domain); the probe
+    series stops when the domain has moved past probe_col."""
     p = sim.params
     c2 = p.c0 * p.c0
-    pmax = np.full(p.nx, -np.inf)
+    ncols = p.nx if window is None else int(path_cells)
+    pmax = np.full(ncols, -np.inf)
     ts, ps = [], []
+    if window is not None:
+        from . import fvna
+        win = fvna.fvna_window(float(window["t1"]), int(window["check_every"]), int(window["quantum"]))
+        state = fvna.fvna_window_state(0, 0)
+    x_off = 0
     for _ in range(max_steps):
         st = sim.fvna_get_stats()
         if st["t"] >= t_end:
             break
-        sim.fvna_step(1)
+        if window is None:
+            sim.fvna_step(1)
+        else:
+            sim.fvna_step_window(win, state, 1)
+            x_off = int(state.x_off)
+        if x_off >= ncols:
+            break
         rp, _, _ = sim.fvna_get_window(0, row, p.nx, 1)
         prow = rp[0] * c2
-        np.maximum(pmax, prow, out=pmax)
-        if probe_col is not None:
+        n = min(p.nx, ncols - x_off)
+        np.maximum(pmax[x_off:x_off + n], prow[:n], out=pmax[x_off:x_off + n])
+        if probe_col is not None and x_off <= probe_col < x_off + p.nx:
             ts.append(sim.fvna_get_stats()["t"])
-            ps.append(prow[probe_col])
+            ps.append(prow[probe_col - x_off])
     return pmax, np.array(ts), np.array(ps)
 
 
-def spectrum(t, p, freq, n=8):
-    """Amplitudes of harmonics 1..n of a transient p(t) sampled at times t
-    (nonuniform), by the trapezoidal Fourier integral over the whole record
-    scaled to amplitude units of a burst: |2/T int p e^{-2 pi i k f t} dt|
-    with T the record length."""
-    return harmonics(t, p, freq, n)
+def spectrum(t, p, freq, n=8, packet_cycles=4.0):
+    """Amplitudes of harmonics 1..n of a packet p(t) sampled at times t
+    (nonuniform, the record covering the whole packet): the trapezoidal
+    Fourier integral |2/D int p e^{-2 pi i k f t} dt| with D the equivalent
+    duration of the envelope exp(-(f t / W)^10), int exp(-(f t / W)^10) dt =
+    (2 W / f) Gamma(1.1), so that a carrier A w(t) sin(2 pi f t) gives A at
+    k = 1 whatever the record length."""
+    t = np.asarray(t)
+    w = np.empty_like(t)
+    w[1:-1] = 0.5 * (t[2:] - t[:-2])
+    w[0] = 0.5 * (t[1] - t[0])
+    w[-1] = 0.5 * (t[-1] - t[-2])
+    D = 2.0 * packet_cycles * math.gamma(1.1) / freq
+    return np.array([abs(2.0 / D * np.sum(w * p * np.exp(-2j * np.pi * k * freq * t)))
+                     for k in range(1, n + 1)])

@@ -30,7 +30,8 @@ BCS = {"periodic": BC_PERIODIC, "extrap0": BC_EXTRAP0, "reflect": BC_REFLECT,
 
 EXPORTS = [
     "fvna_workspace_size", "fvna_create", "fvna_set_bc", "fvna_set_source", "fvna_set_taylor",
-    "fvna_set_state", "fvna_set_clock", "fvna_step", "fvna_sync", "fvna_get_state", "fvna_get_window",
+    "fvna_set_state", "fvna_set_clock", "fvna_step", "fvna_sync", "fvna_shift", "fvna_step_window",
+    "fvna_get_state", "fvna_get_window",
     "fvna_get_stats", "fvna_sums", "fvna_time_step_kernel", "fvna_autotune", "fvna_get_tile_rows",
     "fvna_last_error", "fvna_destroy", "fvna_batch_create", "fvna_batch_set_state",
     "fvna_batch_step", "fvna_batch_sync", "fvna_batch_get_state", "fvna_batch_get_stats",
@@ -58,6 +59,14 @@ class fvna_source(ctypes.Structure):
 
 
 ENVELOPES = {"ramp": 0, "packet": 1}
+
+
+class fvna_window(ctypes.Structure):
+    _fields_ = [("t1", ctypes.c_double), ("check_every", ctypes.c_int32), ("quantum", ctypes.c_int32)]
+
+
+class fvna_window_state(ctypes.Structure):
+    _fields_ = [("x_off", ctypes.c_int64), ("phase", ctypes.c_int64)]
 
 
 class fvna_stats(ctypes.Structure):
@@ -90,6 +99,8 @@ def _load():
         "fvna_set_clock": (st, [vp, d, d]),
         "fvna_step": (st, [vp, i64]),
         "fvna_sync": (st, [vp]),
+        "fvna_shift": (st, [vp, i32]),
+        "fvna_step_window": (st, [vp, P(fvna_window), P(fvna_window_state), i64]),
         "fvna_get_state": (st, [vp, dp, dp, dp]),
         "fvna_get_window": (st, [vp, i32, i32, i32, i32, dp, dp, dp]),
         "fvna_get_stats": (st, [vp, P(fvna_stats)]),
@@ -226,6 +237,14 @@ class Sim:
     def fvna_sync(self, allow_device_errors=False):
         allow = (E_NONHYPERBOLIC, E_NONFINITE, E_RETRIES) if allow_device_errors else ()
         return check(lib.fvna_sync(self.handle), allow)
+
+    def fvna_shift(self, ncols):
+        check(lib.fvna_shift(self.handle, int(ncols)))
+
+    def fvna_step_window(self, window, state, nsteps):
+        """window: fvna_window (t1 [s], check_every, quantum); state:
+        fvna_window_state, updated in place."""
+        check(lib.fvna_step_window(self.handle, ctypes.byref(window), ctypes.byref(state), int(nsteps)))
 
     def fvna_get_state(self, allow_device_errors=False):
         out = [np.empty(self.shape, dtype=np.float64) for _ in range(3)]

@@ -125,32 +125,46 @@ SOFT_TISSUE = {"c0": 1540.0, "rho0": 1000.0, "beta": 4.8, "delta": 6.4117e-4}
 PACKET_FREQ = 1.1e6
 
 
-def hifu_packet(eta=20, a=30.0, length_wl=60.0, margin_wl=10.0, cfl_target=0.9, precision="f64"):
-    """The focused wave-packet experiment of Sec. 4.2 on a fixed domain
-    (lengths in wavelengths, eta cells per wavelength): planar geometry, x1
-    along the propagation axis over length_wl, x2 transverse over a +
-    margin_wl with the symmetry line x2 = 0 reflecting; on x1 = 0 the source
-    of eq. hifuBC over 0 <= x2 <= a with focal length F = 50, amplitude
-    A = 4.217e-4 (1.00 MPa) and the packet envelope (half-width 4 periods);
-    zero-order extrapolation elsewhere.  The run starts at t0 = -6 periods,
-    where the envelope is 9e-26, and ends when the packet has crossed the
-    domain (t_end).  At t = +6 periods, when the packet has left the source,
-    the second stage begins: the whole border x1 = 0 is extrapolating."""
+def hifu_packet(eta=20, a=30.0, length_wl=60.0, margin_wl=10.0, cfl_target=0.9, precision="f64",
+                window_wl=None):
+    """The focused wave-packet experiment of Sec. 4.2 (lengths in wavelengths,
+    eta cells per wavelength): planar geometry, x1 along the propagation axis,
+    x2 transverse over a + margin_wl with the symmetry line x2 = 0 reflecting;
+    on x1 = 0 the source of eq. hifuBC over 0 <= x2 <= a with focal length
+    F = 50, amplitude A = 4.217e-4 (1.00 MPa) and the packet envelope
+    (half-width 4 periods); zero-order extrapolation elsewhere.  The run
+    starts at t0 = -6 periods, where the envelope is 9e-26; t_end = length_wl +
+    6.5 periods, when the whole packet has passed x1 = length_wl.
+
+    window_wl None: a fixed domain length_wl long; the second stage (the whole
+    border x1 = 0 extrapolating) starts at t = +6 periods, when the packet has
+    left the source.  window_wl = L: the moving domain of Sec. 4, L
+    wavelengths long: still until the packet centre reaches its middle at
+    t1 = L/2 periods (also the start of the second stage), then following the
+    packet at c0, checked and moved in quarter-wavelength jumps; length_wl is
+    then the length of the path covered (w["path_cells"])."""
     med = dict(SOFT_TISSUE)
     lam = med["c0"] / PACKET_FREQ
     dx = lam / eta
-    nx = int(round(length_wl * eta))
+    path = int(round(length_wl * eta))
+    nx = path if window_wl is None else int(round(window_wl * eta))
     ny = int(round((a + margin_wl) * eta))
     z = np.zeros((ny, nx))
+    t2 = (6.0 if window_wl is None else 0.5 * window_wl) / PACKET_FREQ
     src = {"freq": PACKET_FREQ, "p_surface": 4.217e-4 * _p0(med), "focal_length": 50.0 * lam,
-           "aperture": a * lam, "envelope": "packet", "packet_cycles": 4.0,
-           "stage2_time": 6.0 / PACKET_FREQ}
+           "aperture": a * lam, "envelope": "packet", "packet_cycles": 4.0, "stage2_time": t2}
     t0 = -6.0 / PACKET_FREQ
     t_end = (length_wl + 6.5) / PACKET_FREQ
-    return {"name": f"hifu-packet eta={eta} a={a:g} {nx}x{ny}", "nx": nx, "ny": ny, "dx": dx,
-            "medium": med, "bc": ("source", "extrap0", "reflect", "extrap0"), "geometry": "planar",
-            "precision": precision, "cfl_target": cfl_target, "cfl_max": 1.0, "source": src,
-            "t0": t0, "t_end": t_end, "wavelength": lam, "eta": eta, "state": (z, z.copy(), z.copy())}
+    name = f"hifu-packet eta={eta} a={a:g} {nx}x{ny}" + ("" if window_wl is None else f" moving over {path}")
+    w = {"name": name, "nx": nx, "ny": ny, "dx": dx,
+         "medium": med, "bc": ("source", "extrap0", "reflect", "extrap0"), "geometry": "planar",
+         "precision": precision, "cfl_target": cfl_target, "cfl_max": 1.0, "source": src,
+         "t0": t0, "t_end": t_end, "wavelength": lam, "eta": eta, "path_cells": path,
+         "state": (z, z.copy(), z.copy())}
+    if window_wl is not None:
+        q = max(4, int(round(eta / 4)))
+        w["window"] = {"t1": t2, "check_every": q, "quantum": q}
+    return w
 
 
 def c4_batch(n=64, seed=4, size_range=(256, 2048), steps=1000):

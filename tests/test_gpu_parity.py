@@ -10,7 +10,7 @@ import sys
 import numpy as np
 import pytest
 
-from common import max_rel, pulse_workload, run_gpu, run_oracle
+from common import dimless_state, max_rel, oracle_params, pulse_workload, run_gpu, run_oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -294,3 +294,68 @@ def test_axisymmetric_noise_bounded_at_cfl_099(precision):
         s.fvna_step(1000)
         R = s.fvna_get_state()[0] / med["rho0"]
         assert np.max(np.abs(R)) < 2 * amp
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32", "f32_f16store", "f32_bf16store"])
+def test_shift_moves_the_stored_state_exactly(precision):
+    """fvna_shift against the definition of a move, on the exported state
+    (bit for bit: the move copies stored values), several moves in a row,
+    ragged width; clock and statistics untouched; bad arguments refused."""
+    from paper_1311_3004_amd import fvna
+    w = pulse_workload(173, 45, ("extrap0", "reflect", "reflect", "extrap0"), seed=21)
+    _say(f"case: shift {precision} 173x45")
+    _, _, sim = run_gpu(w, 3, precision)
+    prev = sim.fvna_get_state()
+    st0 = sim.fvna_get_stats()
+    for k in (0, 1, 37, 64, 70, 173):
+        sim.fvna_shift(k)
+        cur = sim.fvna_get_state()
+        for a, b in zip(prev, cur):
+            want = np.zeros_like(a)
+            want[:, : a.shape[1] - k] = a[:, k:]
+            assert np.array_equal(b, want), k
+        prev = cur
+    st1 = sim.fvna_get_stats()
+    assert st1["t"] == st0["t"] and st1["steps"] == st0["steps"] and st1["dt_next"] == st0["dt_next"]
+    for bad in (-1, 174):
+        with pytest.raises(fvna.FvnaError):
+            sim.fvna_shift(bad)
+    sim.fvna_destroy()
+    wp = pulse_workload(64, 40, ("periodic", "periodic", "extrap0", "extrap0"), seed=22)
+    _, _, sp = run_gpu(wp, 1, precision)
+    with pytest.raises(fvna.FvnaError):
+        sp.fvna_shift(3)
+    sp.fvna_destroy()
+
+
+def test_moving_domain_vs_oracle(orc):
+    """The moving domain of Sec. 4 on the focused packet (10 cells per
+    wavelength, aperture 4, a domain 16 wavelengths long): still until the
+    packet centre reaches its middle, then moved in quarter-wavelength jumps
+    checked every 3 steps (phase carried across calls of uneven length), FP64,
+    against the oracle's two-stage run."""
+    from paper_1311_3004_amd import fvna, inputs
+    w = inputs.hifu_packet(eta=10, a=4.0, length_wl=40.0, margin_wl=3.0, window_wl=16.0)
+    w["window"] = dict(w["window"], check_every=3)
+    _say(f"case: {w['name']} moving domain")
+    med = w["medium"]
+    sim = fvna.sim_from_workload(w, precision="f64")
+    win = fvna.fvna_window(w["window"]["t1"], w["window"]["check_every"], w["window"]["quantum"])
+    state = fvna.fvna_window_state(0, 0)
+    for n in (100, 1, 7, 2, 190):
+        sim.fvna_step_window(win, state, n)
+    g = sim.fvna_get_state()
+    g = (g[0] / med["rho0"], g[1] / (med["rho0"] * med["c0"]), g[2] / (med["rho0"] * med["c0"]))
+    st = sim.fvna_get_stats()
+    p = oracle_params(orc, w)
+    R, M, N = dimless_state(w)
+    scale = med["c0"] / w["dx"]
+    R1, M1, N1, info, x_off = orc.run_window(p, R, M, N, 300, w["t0"] * scale, 0.0,
+                                             w["window"]["t1"] * scale, 3, w["window"]["quantum"])
+    assert st["status"] == 0 and info["status"] == 0 and st["steps"] == 300
+    assert state.x_off == x_off and x_off >= 40
+    peak = np.max(np.abs(R1))
+    err = max_rel(g, (R1, M1, N1), peak=peak)
+    _say(f"  x_off {x_off}, max rel err {err:.3e}")
+    assert err <= 1e-10
+    sim.fvna_destroy()
