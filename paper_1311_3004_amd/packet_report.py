@@ -14,6 +14,7 @@ amplitudes of harmonics 1..8 at the probe (x1, x2) = (1, 0).
     python -m paper_1311_3004_amd.packet_report all             # a x eta x nu_W of Sec. 4.2
     python -m paper_1311_3004_amd.packet_report all f32
     python -m paper_1311_3004_amd.packet_report all f64 window
+    python -m paper_1311_3004_amd.packet_report 30,82,0.99 f32 window    # one case
 """
 import itertools
 import json
@@ -60,7 +61,13 @@ def main(argv):
     which = argv[1] if len(argv) > 1 else "extremes"
     precision = argv[2] if len(argv) > 2 else "f64"
     window_wl = WINDOW_WL if len(argv) > 3 and argv[3] == "window" else None
-    cases = EXTREMES if which == "extremes" else list(itertools.product(A_VALUES, ETAS, NUS))
+    if which == "extremes":
+        cases = EXTREMES
+    elif which == "all":
+        cases = list(itertools.product(A_VALUES, ETAS, NUS))
+    else:
+        a, eta, nu = which.split(",")
+        cases = [(float(a), int(eta), float(nu))]
     for a, eta, nu in cases:
         print(json.dumps(run(a, eta, nu, precision, window_wl=window_wl)), flush=True)
 
