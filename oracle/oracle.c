@@ -396,6 +396,17 @@ static void fill_ghosts_y(const orc_params *p, double t, field_t *g, int layers)
         }
 }
 
+/* Ghost rows of the x1-swept state Q*: as fill_ghosts_y, except on sides with
+ * analytic (Taylor) data, whose rows the step has already filled. */
+static void fill_ghosts_y_q1(const orc_params *p, double t, field_t *g, int layers)
+{
+    for (int i = 0; i < g->nx; i++)
+        for (int l = 1; l <= layers; l++) {
+            if (p->bc[2] != BC_TAYLOR) set_ghost(p, t, g, 2, i, -l, l);
+            if (p->bc[3] != BC_TAYLOR) set_ghost(p, t, g, 3, i, g->ny - 1 + l, l);
+        }
+}
+
 /* ------------------------------------------------------------------------- */
 /* Source step (eq. fs:source): forward Euler in time, second-order central  */
 /* differences in space.                                                     */
@@ -519,9 +530,38 @@ static int attempt(const orc_params *p, work_t *w, double t, double dt, double *
             w->b.R[d] = w->or_[i]; w->b.M[d] = w->on[i]; w->b.N[d] = w->ot[i];
         }
     }
+    /* Ghost rows of Q* on sides with analytic (Taylor) data: the x1 sweep
+     * applied to the analytic Q^n of those rows (their own x ghosts by the
+     * x side rules), so that the x2 sweep meets ghost values that went through
+     * the same first fractional step as the interior.  Their interfaces do not
+     * enter the CFL maximum. */
+    for (int side = 2; side <= 3; side++) {
+        if (p->bc[side] != BC_TAYLOR) continue;
+        for (int l = 1; l <= 2; l++) {
+            int j = side == 2 ? -l : ny - 1 + l;
+            for (int i = 0; i < nx; i++) set_ghost(p, t, &w->a, side, i, j, l);
+            for (int l2 = 1; l2 <= 2; l2++) {
+                set_ghost(p, t, &w->a, 0, -l2, j, l2);
+                set_ghost(p, t, &w->a, 1, nx - 1 + l2, j, l2);
+            }
+            for (int k = 0; k < nx + 2 * GH; k++) {
+                size_t s = idx(&w->a, k - GH, j);
+                w->lr[k] = w->a.R[s]; w->ln[k] = w->a.M[s]; w->lt[k] = w->a.N[s];
+            }
+            double ghost_smax = 0.0;
+            int ghost_bad = 0;
+            e = sweep_line(p->beta, dt, nx, w->lr, w->ln, w->lt, w->or_, w->on, w->ot, w->f,
+                           &ghost_smax, &ghost_bad);
+            if (e) return e;
+            for (int i = 0; i < nx; i++) {
+                size_t d = idx(&w->b, i, j);
+                w->b.R[d] = w->or_[i]; w->b.M[d] = w->on[i]; w->b.N[d] = w->ot[i];
+            }
+        }
+    }
     if (p->geometry == GEOM_AXISYM) geometric_half_step(p, 0.5 * dt, &w->b);
     /* x2 sweep on Q*: same scheme with components 2 and 3 swapped */
-    fill_ghosts_y(p, t, &w->b, 2);
+    fill_ghosts_y_q1(p, t, &w->b, 2);
     for (int i = 0; i < nx; i++) {
         for (int k = 0; k < ny + 2 * GH; k++) {
             size_t s = idx(&w->b, i, k - GH);

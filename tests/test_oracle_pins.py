@@ -643,3 +643,35 @@ def test_moving_domain_matches_the_fixed_domain_inside_the_window(orc):
         ref = f_[:, x_off:x_off + nxw]
         assert np.max(np.abs(w_[:, keep] - ref[:, keep])) <= 1e-13 * peak
     assert np.max(np.abs(Rf[:, x_off:x_off + nxw])) >= 0.99 * peak   # the packet is inside
+
+
+# -- Ghost rows of the intermediate state on sides with analytic data -----------
+
+def test_analytic_y_sides_step_the_exact_plane_wave_like_periodic_rows(orc):
+    """From the exact plane wave along x1 (theta_T = 0, eq. OurTaylorS,
+    inviscid) at time t_n, one step with analytic data on all four sides must
+    equal, bit for bit, the step with periodic rows: the state is independent
+    of x2, so the x2 sweep has nothing to do.  That holds only if the ghost
+    rows the x2 sweep reads went through the same x1 sweep as the interior;
+    analytic Q^n written straight into them leaves an O(dt) jump at the sides
+    (and the analytic state at t_n+1 an O(dt^2) one), which the x2 sweep
+    turns into a change of the outer rows and a non-zero N."""
+    eta, amp, nx, ny, x0 = 6.0, 1e-3, 90, 12, 30.0
+    x = np.arange(nx) + 0.5
+    tay = {"amp": amp, "width": eta, "x0": x0}
+    pa = orc.make_params(nx, ny, 4.0, 0.0, bc=("taylor",) * 4, taylor=tay, fixed_dt=True)
+    pp = orc.make_params(nx, ny, 4.0, 0.0, bc=("taylor", "taylor", "periodic", "periodic"), taylor=tay,
+                         fixed_dt=True)
+    for tn in (0.0, 7.25, 20.5):
+        # the exact state from the oracle's own analytic data (its tanh, so the
+        # interior and the ghost rows agree to the last bit)
+        row = np.array([orc.taylor_value(pa, xx, 0.5, tn) for xx in x])
+        R = np.broadcast_to(row[:, 0], (ny, nx)).copy()
+        M = np.broadcast_to(row[:, 1], (ny, nx)).copy()
+        N = np.zeros_like(R)
+        Ra, Ma, Na, ia = orc.run(pa, R, M, N, 1, t=tn, dt=0.9)
+        Rp, Mp, Np, ip = orc.run(pp, R, M, N, 1, t=tn, dt=0.9)
+        assert ia["status"] == 0 and ip["status"] == 0
+        for a, b in ((Ra, Rp), (Ma, Mp), (Na, Np)):
+            assert np.array_equal(a, b)
+        assert np.all(Na == 0.0) and np.max(np.abs(Ra - R)) > 1e-3 * amp
