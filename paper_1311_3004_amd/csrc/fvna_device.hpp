@@ -663,11 +663,11 @@ __device__ __forceinline__ void march(const SimDesc& d, int strip, int seg)
     };
 
     // ---- x1 sweep of one row (lane-parallel) ----
-    auto xsweep = [&](int vr, S ra, S rb, S rc) -> Cell<T> {
-        Cell<T> q;
-        q.R = C::ld(ra, sc0);
-        q.M = C::ld(rb, sc1);
-        q.N = C::ld(rc, sc2);
+    // GHOST: a ghost row of a side with analytic data (its Q^n analytic, the
+    // x side rules applied to it as to a real row); its interfaces do not
+    // enter the CFL maximum and it takes no geometric term.
+    auto xsweep_core = [&](auto ghost, int vr, Cell<T> q) -> Cell<T> {
+        constexpr bool GHOST = decltype(ghost)::value;
         if (EDGE) {
             q.M *= msign;
             if (xkind == 1) {
@@ -675,7 +675,8 @@ __device__ __forceinline__ void march(const SimDesc& d, int strip, int seg)
                 taylor_at(d, col + 0.5, vr + 0.5, tn, R, M, N);
                 q.R = (T)R; q.M = (T)M; q.N = (T)N;
             } else if (xkind == 2) {
-                if (vr + 0.5 <= src_clk.ap) source_at<T>(d, vr, src_clk, q.R, q.M, q.N);
+                const bool row_ok = !GHOST || (unsigned)vr < (unsigned)ny;
+                if (row_ok && vr + 0.5 <= src_clk.ap) source_at<T>(d, vr, src_clk, q.R, q.M, q.N);
             }
         }
         const T irho = rcp(T(1) + q.R);
@@ -685,7 +686,7 @@ __device__ __forceinline__ void march(const SimDesc& d, int strip, int seg)
         Wave<T> w;
         T D;
         const T spd = roe(RL, ML, NL, uL, vL, q.R, q.M, q.N, u, v, beta, w, D);
-        xacc.add(spd, D);
+        if constexpr (!GHOST) xacc.add(spd, D);
         // waves of the interface to the right -> products with it; the lane
         // to the left supplies the products with the interface below
         Wave<T> wr;
@@ -703,8 +704,23 @@ __device__ __forceinline__ void march(const SimDesc& d, int strip, int seg)
         o2.R = fma_(-dt, g0 + Gp[0], q.R);
         o2.M = fma_(-dt, g1 + Gp[1], q.M);
         o2.N = fma_(-dt, g2 + Gp[2], q.N);
-        if constexpr (AXI) geometric_half_step(o2, hdt * rcp(T(vr) + T(0.5)));
+        if constexpr (AXI && !GHOST) geometric_half_step(o2, hdt * rcp(T(vr) + T(0.5)));
         return o2;
+    };
+    auto xsweep = [&](int vr, S ra, S rb, S rc) -> Cell<T> {
+        Cell<T> q;
+        q.R = C::ld(ra, sc0);
+        q.M = C::ld(rb, sc1);
+        q.N = C::ld(rc, sc2);
+        return xsweep_core(Flag<false>{}, vr, q);
+    };
+    // Q* of ghost row vr of a side with analytic (Taylor) data: the x1 sweep
+    // of the analytic Q^n of that row, so that the x2 sweep meets ghost values
+    // that went through the same first fractional step as the interior
+    auto xsweep_taylor_ghost = [&](int vr) -> Cell<T> {
+        double R, M, N;
+        taylor_at(d, scol + 0.5, vr + 0.5, tn, R, M, N);
+        return xsweep_core(Flag<true>{}, vr, Cell<T>{(T)R, (T)M, (T)N});
     };
 
     // analytic (Taylor) velocities of a ghost cell
@@ -874,9 +890,7 @@ __device__ __forceinline__ void march(const SimDesc& d, int strip, int seg)
             for (int k = HALO; k >= 1; --k) {       // rows -3, -2, -1
                 Cell<T> q;
                 if (b == BC_TAYLOR) {
-                    double R, M, N;
-                    taylor_at(d, col + 0.5, -k + 0.5, tn, R, M, N);
-                    q.R = (T)R; q.M = (T)M; q.N = (T)N;
+                    q = xsweep_taylor_ghost(-k);
                 } else if (b == BC_REFLECT) {
                     q = (k == 1) ? q0 : q1;
                     q.N = -q.N;
@@ -923,9 +937,7 @@ __device__ __forceinline__ void march(const SimDesc& d, int strip, int seg)
             const int b = d.bc[3];
             Cell<T> q = A.q;                           // zero-order extrapolation of Q*_{ny-1}
             if (b == BC_TAYLOR) {
-                double R, M, N;
-                taylor_at(d, col + 0.5, v + 0.5, tn, R, M, N);
-                q.R = (T)R; q.M = (T)M; q.N = (T)N;
+                q = xsweep_taylor_ghost(v);
             } else if (b == BC_REFLECT) {
                 if (v == ny) { q = A.q; q.N = -q.N; }
                 else if (v == ny + 1) { q = stash; q.N = -q.N; }

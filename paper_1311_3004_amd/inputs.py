@@ -85,6 +85,53 @@ def c1_taylor_fp64(nx=256, ny=256, seed=1):
             "state": (rp, mx, my)}
 
 
+RISE_10_90 = 2.0 * np.arctanh(0.8)     # 10%-90% rise of tanh, in tanh units (2.197)
+
+
+def taylor_oblique(eta, theta, cfl_target=0.9, reading="rise", amplitude=1e-7, travel=100.0,
+                   margin=6.0, precision="f64", medium=None):
+    """The Taylor-shock study of Sec. 4.1: p'/p0 = -a tanh((xi - c0 t)/w) with
+    xi the distance along the propagation direction (cos theta, sin theta),
+    a = 1e-7 (the paper's delta~/beta), w = delta / (c0 beta a) the tanh unit;
+    M = R cos theta, N = R sin theta (eq. OurTaylorS rotated); analytic data
+    on all four sides.
+
+    The paper's length unit L and mesh parameter eta = cells per L: reading
+    "rise" takes L as the 10%-90% rise of the profile (2.197 tanh units, the
+    paper's own definition of L), reading "tanh" takes L = w (the unit in
+    which its formula tanh(x - t) is written).  The front starts through the
+    point (margin, margin) L from the lower-left corner and travels `travel`
+    L; the domain covers the whole path with `margin` L to spare, so the
+    front never meets the sides.  The errors are read on the 10-L line along
+    the propagation direction centred on the analytic front at t_end
+    (eq. error)."""
+    med = dict(WATER if medium is None else medium)
+    w_t = med["delta"] / (med["c0"] * med["beta"] * amplitude)       # tanh unit [m]
+    L = w_t * (RISE_10_90 if reading == "rise" else 1.0)
+    dx = L / eta
+    c, s = float(np.cos(theta)), float(np.sin(theta))
+    if abs(s) < 1e-15:
+        s = 0.0
+    nx = int(np.ceil((2 * margin + travel * c) * eta))
+    ny = int(np.ceil((2 * margin + travel * s) * eta))
+    px, py = margin * L, margin * L                                  # front at t = 0
+    x0 = px + py * s / c                                             # xi = 0 through (px, py)
+    x = (np.arange(nx) + 0.5) * dx
+    y = (np.arange(ny) + 0.5) * dx
+    xi = (x[None, :] - x0) * c + y[:, None] * s
+    R = -amplitude * np.tanh(xi / w_t)
+    p0 = _p0(med)
+    rp = R * med["rho0"]
+    mom = R * med["rho0"] * med["c0"]
+    return {"name": f"taylor-oblique theta={theta:.4f} eta={eta} {reading} {nx}x{ny}", "nx": nx, "ny": ny,
+            "dx": dx, "medium": med, "bc": ("taylor",) * 4, "geometry": "planar", "precision": precision,
+            "cfl_target": cfl_target, "cfl_max": 1.0,
+            "taylor": {"amplitude_pa": amplitude * p0, "x0_m": x0, "angle": theta},
+            "t_end": travel * L / med["c0"], "front0_m": (px, py), "unit_m": L, "tanh_unit_m": w_t,
+            "eta": eta, "theta": theta, "amplitude": amplitude,
+            "state": (rp, mom * c, mom * s)}
+
+
 def c2_pulse_fp32(nx=4096, ny=4096, seed=2):
     """FP32 Cartesian 4096^2: 2 MPa Gaussian (sigma 20 cells) at a seed-chosen
     centre in [1536, 2560)^2 plus 0.5% white noise, absorbing (zero-order
