@@ -72,7 +72,11 @@ typedef enum { FVNA_F64 = 0, FVNA_F32 = 1, FVNA_F32_F16STORE = 2, FVNA_F32_BF16S
  *   REFLECT:  mirror with the momentum normal to the side negated (Sec. 4.2);
  *             the r = 0 axis of the axisymmetric geometry.
  *   TAYLOR:   the analytic Taylor shock-like profile of eq. OurTaylorS,
- *             set by fvna_set_taylor, evaluated at the ghost-cell centre.
+ *             set by fvna_set_taylor, evaluated at the ghost-cell centre at
+ *             t_n.  On a y side the ghost rows that the x2 sweep reads hold
+ *             the x1 sweep of that analytic data (the same first fractional
+ *             step as the interior) rather than the data themselves.
+ * Side data enter at t_n, the start of the step (all kinds).
  *   SOURCE:   the focused boundary source of eq. hifuBC on side x- only,
  *             set by fvna_set_source; zero-order extrapolation outside the
  *             aperture. */
