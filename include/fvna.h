@@ -228,6 +228,33 @@ typedef struct {
  * sides that cannot move (as fvna_shift). */
 fvna_status fvna_step_window(fvna_ctx* c, const fvna_window* w, fvna_window_state* st, int64_t nsteps);
 
+/* Recorder of the on-axis quantities of Sec. 4.2 (pressure maxima over the
+ * propagation axis, the time series at a probe) without a host round trip per
+ * step.  While set, every attempt of fvna_step, fvna_sync and
+ * fvna_step_window is followed by a small kernel that, once at least one step
+ * has been accepted since fvna_set_recorder,
+ *   row_max[x_off + i] = max(row_max[x_off + i], rho'(i, row))  for x_off + i < path_len,
+ * with x_off the cells the domain has moved (fvna_shift) since the state was
+ * set, and writes t and rho'(probe, row) of the latest accepted step k
+ * (counted from 1 at fvna_set_recorder) to probe_t[k - 1], probe_rho[k - 1]
+ * for k <= capacity while the probe column is inside the domain.  rho' in
+ * kg/m^3 (p' = c0^2 rho'), t in s.  Rejected attempts leave everything as it
+ * was (the kernel is idempotent).  The arrays are caller-owned device memory
+ * and must outlive the recording; the caller initialises row_max (e.g. to
+ * -inf) and the probe arrays.  fvna_set_recorder synchronises the stream;
+ * NULL stops recording.  FVNA_E_INVALID for a row outside the grid, missing
+ * arrays, path_len < 1 or probe_col < -1 (-1: no probe). */
+typedef struct {
+    int32_t row;
+    int32_t probe_col;         /* path column, or -1 */
+    int64_t path_len;
+    double* row_max;           /* device, path_len doubles */
+    double* probe_t;           /* device, capacity doubles (or NULL, capacity 0) */
+    double* probe_rho;         /* device, capacity doubles */
+    int64_t capacity;
+} fvna_recorder;
+fvna_status fvna_set_recorder(fvna_ctx* c, const fvna_recorder* r);
+
 /* Synchronise and copy the current state out (same units and layout as set_state). */
 fvna_status fvna_get_state(fvna_ctx* c, double* rho_p, double* mom_x, double* mom_y);
 

@@ -69,7 +69,8 @@ struct Clock {
     int retries;                 // consecutive rejections
     double nu_last, nu_mean, nu_m2;   // CFL statistics (Welford)
     long long nu_count;
-    double pad[2];
+    long long x_off;             // cells the domain has moved since the state was set
+    double pad;
 };
 
 // Everything a wavefront needs to know about its simulation.

@@ -309,10 +309,47 @@ __global__ __launch_bounds__(256) void k_shift(SimDesc d, int ncols)
     }
 }
 
-__global__ void k_flip(Clock* c)
+__global__ void k_flip(Clock* c, int ncols)
 {
-    if (threadIdx.x == 0) c->cur ^= 1;
+    if (threadIdx.x == 0) {
+        c->cur ^= 1;
+        c->x_off += ncols;
+    }
 }
+
+// Recorder: after an attempt, the running maximum of rho' along one grid row,
+// kept per column of the path the (possibly moving) domain covers, and rho'
+// and t at one probe column after every accepted step.  Idempotent: after a
+// rejected or empty attempt it sees the state and step count it saw before,
+// so it can follow every attempt without knowing which were accepted.
+struct RecDesc {
+    int row, probe_col;
+    long long path_len, base, capacity;
+    double* row_max;
+    double* probe_t;
+    double* probe_rho;
+    double rho0, t_unit;
+};
+
+template <typename S, typename T>
+__global__ __launch_bounds__(256) void k_record(SimDesc d, RecDesc r)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= d.nx) return;
+    const Clock* clk = d.clk;
+    const long long k = clk->accepted - r.base - 1;   // index of the latest accepted step
+    if (k < 0) return;
+    const S* R = (const S*)d.buf[clk->cur] + (size_t)r.row * d.pitch;
+    const double rho = (double)Codec<S, T>::ld(R[i], d.scale[0]) * r.rho0;
+    const long long pc = clk->x_off + i;                // path column of this cell
+    if (pc < r.path_len) r.row_max[pc] = fmax(r.row_max[pc], rho);
+    if (pc == r.probe_col && k < r.capacity) {
+        r.probe_t[k] = clk->t * r.t_unit;
+        r.probe_rho[k] = rho;
+    }
+}
+
+
 
 // Fixed-order FP64 sums: block b sums rows b, b + NB, ... with a fixed
 // thread stride and a fixed tree; the final pass sums the NB partials.
@@ -503,6 +540,7 @@ struct Launcher {
     void (*exp)(const SimDesc&, double*, int, int, int, int, int, double, hipStream_t);
     void (*sums)(const SimDesc&, double*, hipStream_t);
     void (*shift)(const SimDesc&, int, hipStream_t);
+    void (*record)(const SimDesc&, const RecDesc&, hipStream_t);
 };
 
 template <typename S, typename T, int AXI>
@@ -538,7 +576,10 @@ Launcher make_launcher()
     L.shift = [](const SimDesc& d, int ncols, hipStream_t s) {
         const int rows = std::min(3 * d.ny, 65535);
         hipLaunchKernelGGL(k_shift<S>, dim3((d.pitch + 255) / 256, rows), dim3(256), 0, s, d, ncols);
-        hipLaunchKernelGGL(k_flip, dim3(1), dim3(64), 0, s, d.clk);
+        hipLaunchKernelGGL(k_flip, dim3(1), dim3(64), 0, s, d.clk, ncols);
+    };
+    L.record = [](const SimDesc& d, const RecDesc& r, hipStream_t s) {
+        hipLaunchKernelGGL((k_record<S, T>), dim3((d.nx + 255) / 256), dim3(256), 0, s, d, r);
     };
     return L;
 }
@@ -596,7 +637,17 @@ struct fvna_ctx {
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
     int device = 0;
+    bool recording = false;     // a recorder follows every attempt
+    RecDesc rec{};
 };
+
+// One attempt on stream s: the step, the CFL decision, the recorder if any.
+static void launch_attempt(fvna_ctx* c, hipStream_t s)
+{
+    c->L.step(c->d, 0, s);
+    hipLaunchKernelGGL(k_ctrl, dim3(1), dim3(64), 0, s, c->d);
+    if (c->recording) c->L.record(c->d, c->rec, s);
+}
 
 static void drop_graph(fvna_ctx* c)
 {
@@ -610,10 +661,7 @@ static fvna_status build_graph(fvna_ctx* c)
 {
     if (c->exec) return FVNA_OK;
     HIP_TRY(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
-    for (int k = 0; k < GRAPH_CHUNK; ++k) {
-        c->L.step(c->d, 0, c->cap);
-        hipLaunchKernelGGL(k_ctrl, dim3(1), dim3(64), 0, c->cap, c->d);
-    }
+    for (int k = 0; k < GRAPH_CHUNK; ++k) launch_attempt(c, c->cap);
     hipGraph_t g = nullptr;
     HIP_TRY(hipStreamEndCapture(c->cap, &g));
     c->graph = g;
@@ -641,13 +689,15 @@ static fvna_status status_of(int st)
 }
 
 // Reset the clock to (t, dt) and recompute dt from the state if dt <= 0.
-static fvna_status reset_clock(fvna_ctx* c, double t_dimless, double dt_dimless, int cur)
+static fvna_status reset_clock(fvna_ctx* c, double t_dimless, double dt_dimless, int cur,
+                               long long x_off = 0)
 {
     Clock h;
     std::memset(&h, 0, sizeof(h));
     h.t = t_dimless;
     h.dt = dt_dimless > 0.0 ? dt_dimless : 0.0;
     h.cur = cur;
+    h.x_off = x_off;
     HIP_TRY(hipStreamSynchronize(c->stream));
     HIP_TRY(hipMemcpy(c->clk, &h, sizeof(Clock), hipMemcpyHostToDevice));
     if (!(dt_dimless > 0.0)) {
@@ -825,7 +875,7 @@ fvna_status fvna_set_clock(fvna_ctx* c, double t, double dt_next)
     fvna_status s = read_clock(c, &h);
     if (s) return s;
     const fvna_params& p = c->p;
-    return reset_clock(c, t * p.c0 / p.dx, dt_next > 0 ? dt_next * p.c0 / p.dx : 0.0, h.cur);
+    return reset_clock(c, t * p.c0 / p.dx, dt_next > 0 ? dt_next * p.c0 / p.dx : 0.0, h.cur, h.x_off);
 }
 
 // Enqueue exactly `attempts` attempts: whole captured chunks, then single launches.
@@ -834,10 +884,7 @@ static fvna_status enqueue_attempts(fvna_ctx* c, long long attempts)
     fvna_status s = build_graph(c);
     if (s) return s;
     for (long long k = 0; k < attempts / GRAPH_CHUNK; ++k) HIP_TRY(hipGraphLaunch(c->exec, c->stream));
-    for (long long k = 0; k < attempts % GRAPH_CHUNK; ++k) {
-        c->L.step(c->d, 0, c->stream);
-        hipLaunchKernelGGL(k_ctrl, dim3(1), dim3(64), 0, c->stream, c->d);
-    }
+    for (long long k = 0; k < attempts % GRAPH_CHUNK; ++k) launch_attempt(c, c->stream);
     HIP_TRY(hipGetLastError());
     return FVNA_OK;
 }
@@ -865,6 +912,40 @@ fvna_status fvna_sync(fvna_ctx* c)
         if (s) return s;
     }
     return fail(FVNA_E_STATE, "steps still owed after many top-up rounds");
+}
+
+fvna_status fvna_set_recorder(fvna_ctx* c, const fvna_recorder* r)
+{
+    if (!c) return fail(FVNA_E_INVALID, "ctx is NULL");
+    if (!r) {
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        c->recording = false;
+        drop_graph(c);
+        return FVNA_OK;
+    }
+    if (r->row < 0 || r->row >= c->p.ny) return fail(FVNA_E_INVALID, "recorder row outside the grid");
+    if (r->path_len < 1 || !r->row_max) return fail(FVNA_E_INVALID, "recorder needs row_max and path_len >= 1");
+    if (r->capacity < 0 || (r->capacity > 0 && (!r->probe_t || !r->probe_rho)))
+        return fail(FVNA_E_INVALID, "recorder probe arrays missing for capacity > 0");
+    if (r->probe_col < -1) return fail(FVNA_E_INVALID, "probe_col must be >= -1");
+    Clock h;
+    fvna_status s = read_clock(c, &h);
+    if (s) return s;
+    RecDesc d{};
+    d.row = r->row;
+    d.probe_col = r->probe_col;
+    d.path_len = r->path_len;
+    d.base = h.accepted;
+    d.capacity = r->probe_col >= 0 ? r->capacity : 0;
+    d.row_max = r->row_max;
+    d.probe_t = r->probe_t;
+    d.probe_rho = r->probe_rho;
+    d.rho0 = c->p.rho0;
+    d.t_unit = c->p.dx / c->p.c0;
+    c->rec = d;
+    c->recording = true;
+    drop_graph(c);
+    return FVNA_OK;
 }
 
 fvna_status fvna_shift(fvna_ctx* c, int32_t ncols)

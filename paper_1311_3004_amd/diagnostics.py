@@ -177,3 +177,54 @@ def taylor_errors(w, t, R):
     num = R[j, i]
     d = np.abs(num - ref)
     return float(np.sum(d) / np.sum(np.abs(ref))), float(np.max(d) / np.max(np.abs(ref)))
+
+
+def axis_maxima_recorded(sim, t_end, probe_col=None, row=0, window=None, path_cells=None, margin=1.05):
+    """axis_maxima with the library's recorder (fvna_set_recorder): the
+    maxima and the probe series are kept on the device after every step and
+    read once at the end, so the steps run back to back (the stopping rule
+    is the same: the first state with t >= t_end).  The maxima agree with
+    axis_maxima wherever the wave has passed; at columns that entered a
+    moving domain empty and saw only negative values since, axis_maxima also
+    counts the 0 that entered."""
+    import torch
+    from . import fvna
+    p = sim.params
+    c2 = p.c0 * p.c0
+    ncols = p.nx if window is None else int(path_cells)
+    st = sim.fvna_get_stats()
+    cap = 0
+    if probe_col is not None:
+        cap = int((t_end - st["t"]) / st["dt_next"] * margin) + 64
+    dev = sim.device
+    row_max = torch.full((ncols,), -math.inf, dtype=torch.float64, device=dev)
+    probe_t = torch.full((cap,), math.nan, dtype=torch.float64, device=dev) if cap else None
+    probe_rho = torch.full((cap,), math.nan, dtype=torch.float64, device=dev) if cap else None
+    torch.cuda.synchronize(dev)
+    sim.fvna_set_recorder(row, -1 if probe_col is None else probe_col, ncols, row_max, probe_t, probe_rho)
+    if window is not None:
+        win = fvna.fvna_window(float(window["t1"]), int(window["check_every"]), int(window["quantum"]))
+        state = fvna.fvna_window_state(0, 0)
+    try:
+        while True:
+            st = sim.fvna_get_stats()
+            if st["t"] >= t_end:
+                break
+            left = (t_end - st["t"]) / st["dt_next"]
+            n = max(1, int(left) - 2) if left > 4 else 1
+            if window is None:
+                sim.fvna_step(n)
+            else:
+                sim.fvna_step_window(win, state, n)
+                if state.x_off >= ncols:
+                    break
+        sim.fvna_sync()
+    finally:
+        sim.fvna_set_recorder(None)
+    pmax = row_max.cpu().numpy() * c2
+    if not cap:
+        return pmax, np.array([]), np.array([])
+    t = probe_t.cpu().numpy()
+    r = probe_rho.cpu().numpy()
+    keep = ~np.isnan(t)
+    return pmax, t[keep], r[keep] * c2

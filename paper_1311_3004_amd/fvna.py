@@ -31,6 +31,7 @@ BCS = {"periodic": BC_PERIODIC, "extrap0": BC_EXTRAP0, "reflect": BC_REFLECT,
 EXPORTS = [
     "fvna_workspace_size", "fvna_create", "fvna_set_bc", "fvna_set_source", "fvna_set_taylor",
     "fvna_set_state", "fvna_set_clock", "fvna_step", "fvna_sync", "fvna_shift", "fvna_step_window",
+    "fvna_set_recorder",
     "fvna_get_state", "fvna_get_window",
     "fvna_get_stats", "fvna_sums", "fvna_time_step_kernel", "fvna_autotune", "fvna_get_tile_rows",
     "fvna_last_error", "fvna_destroy", "fvna_batch_create", "fvna_batch_set_state",
@@ -69,6 +70,12 @@ class fvna_window_state(ctypes.Structure):
     _fields_ = [("x_off", ctypes.c_int64), ("phase", ctypes.c_int64)]
 
 
+class fvna_recorder(ctypes.Structure):
+    _fields_ = [("row", ctypes.c_int32), ("probe_col", ctypes.c_int32), ("path_len", ctypes.c_int64),
+                ("row_max", ctypes.c_void_p), ("probe_t", ctypes.c_void_p), ("probe_rho", ctypes.c_void_p),
+                ("capacity", ctypes.c_int64)]
+
+
 class fvna_stats(ctypes.Structure):
     _fields_ = [("t", ctypes.c_double), ("dt_next", ctypes.c_double), ("nu_last", ctypes.c_double),
                 ("nu_mean", ctypes.c_double), ("nu_std", ctypes.c_double),
@@ -101,6 +108,7 @@ def _load():
         "fvna_sync": (st, [vp]),
         "fvna_shift": (st, [vp, i32]),
         "fvna_step_window": (st, [vp, P(fvna_window), P(fvna_window_state), i64]),
+        "fvna_set_recorder": (st, [vp, P(fvna_recorder)]),
         "fvna_get_state": (st, [vp, dp, dp, dp]),
         "fvna_get_window": (st, [vp, i32, i32, i32, i32, dp, dp, dp]),
         "fvna_get_stats": (st, [vp, P(fvna_stats)]),
@@ -245,6 +253,22 @@ class Sim:
         """window: fvna_window (t1 [s], check_every, quantum); state:
         fvna_window_state, updated in place."""
         check(lib.fvna_step_window(self.handle, ctypes.byref(window), ctypes.byref(state), int(nsteps)))
+
+    def fvna_set_recorder(self, row=None, probe_col=-1, path_len=0, row_max=None, probe_t=None,
+                          probe_rho=None):
+        """row None stops recording; otherwise row_max (path_len doubles) and the
+        probe arrays are device tensors (torch, float64) that must outlive the
+        recording."""
+        if row is None:
+            check(lib.fvna_set_recorder(self.handle, None))
+            self._rec_keep = None
+            return
+        cap = 0 if probe_t is None else int(probe_t.numel())
+        r = fvna_recorder(int(row), int(probe_col), int(path_len), row_max.data_ptr(),
+                          probe_t.data_ptr() if probe_t is not None else None,
+                          probe_rho.data_ptr() if probe_rho is not None else None, cap)
+        self._rec_keep = (row_max, probe_t, probe_rho)
+        check(lib.fvna_set_recorder(self.handle, ctypes.byref(r)))
 
     def fvna_get_state(self, allow_device_errors=False):
         out = [np.empty(self.shape, dtype=np.float64) for _ in range(3)]

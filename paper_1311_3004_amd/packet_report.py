@@ -5,7 +5,7 @@ For each (a, eta, nu_W) the packet is run from t = -6 periods to t = 100 (it
 travels 100 wavelengths) over a path 105 wavelengths long and a domain a + 10
 wide -- either a fixed domain over the whole path or (window) the moving
 domain of Sec. 4, 24 wavelengths long -- sampling the cells next to the
-symmetry line every step.  One JSON line per
+symmetry line every step (on the device, fvna_set_recorder).  One JSON line per
 run: wall time (including the sampling), steps, cell-updates per second,
 the on-axis peak pressure and its position, the CFL statistics and the
 amplitudes of harmonics 1..8 at the probe (x1, x2) = (1, 0).
@@ -41,8 +41,8 @@ def run(a, eta, nu, precision="f64", t_end_periods=100.0, length_wl=105.0, windo
     w["t_end"] = t_end_periods / inputs.PACKET_FREQ
     t0 = time.time()
     s = fvna.sim_from_workload(w, precision=precision)
-    pmax, t, p = dg.axis_maxima(s, w["t_end"], probe_col=eta - 1, window=w.get("window"),
-                                path_cells=w["path_cells"])
+    pmax, t, p = dg.axis_maxima_recorded(s, w["t_end"], probe_col=eta - 1, window=w.get("window"),
+                                         path_cells=w["path_cells"])
     st = s.fvna_get_stats()
     s.fvna_destroy()
     elapsed = time.time() - t0

@@ -83,7 +83,8 @@ def test_struct_layouts_match_the_header(fv, tmp_path):
     the C compiler gives the header's structs."""
     import subprocess
     structs = {"fvna_params": fv.fvna_params, "fvna_source": fv.fvna_source, "fvna_stats": fv.fvna_stats,
-               "fvna_window": fv.fvna_window, "fvna_window_state": fv.fvna_window_state}
+               "fvna_window": fv.fvna_window, "fvna_window_state": fv.fvna_window_state,
+               "fvna_recorder": fv.fvna_recorder}
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
     for name, cls in structs.items():
         lines.append(f'  printf("{name} %zu\\n", sizeof({name}));')

@@ -322,3 +322,33 @@ def test_taylor_shock_table1_theta0_row():
         assert abs(got[3] - ref[3]) <= 0.01
         for g, w in zip(got[4:], ref[4:]):
             assert abs(g / w - 1.0) <= 0.10
+
+
+@pytest.mark.parametrize("window_wl", [None, 16.0])
+def test_recorder_matches_sampling_every_step(window_wl):
+    """The device recorder (fvna_set_recorder) against copying the on-axis
+    row out after every step, on the focused packet (20 cells per wavelength,
+    a = 10, a 30-wavelength path) on a fixed and on a moving domain: the same
+    steps, the same maxima bit for bit (on the moving domain the host copy
+    also sees the zeros that enter, which can only raise a column's maximum
+    from below zero to zero) and the same probe series."""
+    import time
+    from paper_1311_3004_amd import fvna, inputs, diagnostics as dg
+    w = inputs.hifu_packet(eta=20, a=10.0, length_wl=30.0, margin_wl=5.0, window_wl=window_wl)
+    out = []
+    for fn in (dg.axis_maxima, dg.axis_maxima_recorded):
+        _say(f"case: {w['name']} {fn.__name__}")
+        s = fvna.sim_from_workload(w, precision="f64")
+        t0 = time.time()
+        res = fn(s, w["t_end"], probe_col=19, window=w.get("window"), path_cells=w["path_cells"])
+        st = s.fvna_get_stats()
+        out.append(res + (st, time.time() - t0))
+        s.fvna_destroy()
+    (ph, th, prh, sth, wh), (pd, td, prd, std_, wd) = out
+    _say(f"  steps {sth['steps']} / {std_['steps']}, wall {wh:.2f} s / {wd:.2f} s")
+    assert sth["steps"] == std_["steps"] and sth["t"] == std_["t"]
+    assert np.all((ph == pd) | ((ph == 0.0) & (pd < 0.0)))
+    assert np.max(pd) > 1e5
+    n = min(len(th), len(td))
+    assert abs(len(th) - len(td)) <= (0 if window_wl is None else 1) and n > 100
+    assert np.array_equal(th[:n], td[:n]) and np.array_equal(prh[:n], prd[:n])
