@@ -29,3 +29,62 @@ def test_harmonics_of_a_steady_signal():
     p = 3.0 * np.sin(2 * np.pi * f * t) + 0.5 * np.cos(4 * np.pi * f * t)
     h = dg.harmonics(t, p, f, 3)
     assert abs(h[0] - 3.0) < 1e-4 and abs(h[1] - 0.5) < 1e-4 and h[2] < 1e-4
+
+
+def test_line_cells_follow_the_propagation_direction():
+    """The error line of the oblique Taylor workload: one cell per column (per
+    row past 45 degrees), consecutive, 10 units long, every chosen cell within
+    half a cell (across the line) of the line through the analytic front."""
+    import math
+    from paper_1311_3004_amd import inputs
+    for theta in (0.0, math.pi / 32, math.pi / 8, math.pi / 4, 3 * math.pi / 8):
+        w = inputs.taylor_oblique(10, theta, travel=30.0)
+        t = 0.37 * w["t_end"]
+        i, j = dg.line_cells(w, t)
+        c, s = math.cos(theta), math.sin(theta)
+        major = i if abs(c) >= abs(s) else j
+        assert np.all(np.diff(major) == 1)
+        assert abs(len(major) - 10 * 10 * max(abs(c), abs(s))) <= 1
+        fx = w["front0_m"][0] + w["medium"]["c0"] * t * c
+        fy = w["front0_m"][1] + w["medium"]["c0"] * t * s
+        px, py = (i + 0.5) * w["dx"] - fx, (j + 0.5) * w["dx"] - fy
+        across = np.abs(-s * px + c * py) / w["dx"]
+        assert np.all(across <= 0.5 * (abs(c) + abs(s)) + 1e-9)
+        along = (c * px + s * py) / w["unit_m"]
+        assert np.all(np.abs(along) <= 5.0 + 1e-9)
+
+
+def test_taylor_errors_vanish_on_the_exact_profile_and_see_a_shift():
+    """E1 and Einf of eq. (error) are 0 (to rounding) on the analytic profile
+    at its own time; a profile one cell behind gives E1 = (total variation of
+    the profile, 2a, times the shift in cells, 1) / (sum of |reference| over
+    the line's cells), to first order in the shift."""
+    from paper_1311_3004_amd import inputs
+    w = inputs.taylor_oblique(20, 0.0, travel=10.0, reading="rise")
+    R0 = w["state"][0] / w["medium"]["rho0"]
+    e1, einf = dg.taylor_errors(w, 0.0, R0)
+    assert e1 < 1e-15 and einf < 1e-15
+    t = w["dx"] / w["medium"]["c0"]                    # the analytic front one cell ahead
+    e1, einf = dg.taylor_errors(w, t, R0)
+    i, _ = dg.line_cells(w, t)
+    xi = ((i + 0.5) * w["dx"] - w["taylor"]["x0_m"] - w["medium"]["c0"] * t) / w["tanh_unit_m"]
+    want = 2.0 / np.sum(np.abs(np.tanh(xi)))
+    assert abs(e1 / want - 1.0) < 0.01
+    assert 0.05 < einf < 0.2                           # dx / w = 0.11 at the front
+
+
+def test_packet_workload_geometry():
+    """Fixed and moving domains of the packet workload: the same cells per
+    wavelength and width, the moving one 24 wavelengths long with its second
+    stage at half its length, quarter-wavelength moves, the fixed one
+    switching at +6 periods."""
+    from paper_1311_3004_amd import inputs
+    f = inputs.PACKET_FREQ
+    wf = inputs.hifu_packet(eta=40, a=10.0, length_wl=60.0)
+    wm = inputs.hifu_packet(eta=40, a=10.0, length_wl=60.0, window_wl=24.0)
+    assert wf["ny"] == wm["ny"] == 800 and wf["nx"] == wf["path_cells"] == 2400
+    assert wm["nx"] == 960 and wm["path_cells"] == 2400
+    assert abs(wf["source"]["stage2_time"] * f - 6.0) < 1e-12
+    assert abs(wm["source"]["stage2_time"] * f - 12.0) < 1e-12 and wm["window"]["t1"] == wm["source"]["stage2_time"]
+    assert wm["window"]["quantum"] == wm["window"]["check_every"] == 10
+    assert abs(wf["t0"] * f + 6.0) < 1e-12 and abs(wf["t_end"] * f - 66.5) < 1e-12
