@@ -35,12 +35,12 @@ BYTES_PER_CELL = {"f64": 48, "f32": 24, "f32_f16store": 12, "f32_bf16store": 12}
 # profiles/k_step_f32_gaussian4096.md.  Valid only for the kernel sources
 # whose SHA-256 is recorded here: any other source reports traffic null.
 PMC_TRAFFIC = {
-    "bytes_per_launch": 216.2e6 + 203.1e6,
-    "fetch_bytes": 216.2e6, "write_bytes": 203.1e6,
+    "bytes_per_launch": 216.2e6 + 203.2e6,
+    "fetch_bytes": 216.2e6, "write_bytes": 203.2e6,
     "nx": 4096, "ny": 4096,
     "sources": {
-        "fvna_device.hpp": "18fc2b372331a12b5baea0016179d62b8a875ecd7cb6b520fe3e5a1f0a5dfe0d",
-        "fvna_runtime.hip": "aaeb2e481f2ad4c84e66f7bcec17481ae1dafcd60b303d21e5f5f7b271e8383e",
+        "fvna_device.hpp": "36224bdec71b2149af2a36c7e561432dc6c8d97c03d0f968f7e439323ef7115c",
+        "fvna_runtime.hip": "81331248debaae07efbe8311f94b596b7ab0a8c598f93549c7c276d4e917e5ec",
     },
 }
 

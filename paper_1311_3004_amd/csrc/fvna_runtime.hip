@@ -207,12 +207,14 @@ __device__ Cell<T> cell_at(const SimDesc& d, int i, int j, double t)
 template <typename S, typename T>
 __global__ __launch_bounds__(256) void k_dry(SimDesc d)
 {
+    // rows j = blockIdx.y, + gridDim.y, ... (j = ny: the top x2 interfaces);
+    // each wavefront folds its rows before its single atomic, so one launch
+    // issues a few thousand atomics instead of one per 64 interfaces
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y;
     const double t = d.clk->t;
     const T beta = (T)d.beta;
     Cfl<T> acc;
-    if (i <= d.nx) {
+    for (int j = blockIdx.y; j <= d.ny && i <= d.nx; j += gridDim.y) {
         if (j < d.ny) {
             const Cell<T> a = cell_at<S, T>(d, i - 1, j, t), b = cell_at<S, T>(d, i, j, t);
             const T ia = rcp(T(1) + a.R), ib = rcp(T(1) + b.R);
@@ -557,7 +559,7 @@ Launcher make_launcher()
         hipLaunchKernelGGL((k_step_batch<S, T, AXI>), dim3(blocks), dim3(256), 0, s, descs, tiles, ntiles, force);
     };
     L.dry = [](const SimDesc& d, hipStream_t s) {
-        hipLaunchKernelGGL((k_dry<S, T>), dim3((d.nx + 1 + 255) / 256, d.ny + 1), dim3(256), 0, s, d);
+        hipLaunchKernelGGL((k_dry<S, T>), dim3((d.nx + 1 + 255) / 256, std::min(d.ny + 1, 64)), dim3(256), 0, s, d);
     };
     L.imp = [](const SimDesc& d, const double* src, int field, int row0, int nrows, double denom, int buf,
                hipStream_t s) {
