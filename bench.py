@@ -37,12 +37,31 @@ BYTES_PER_CELL = {"f64": 48, "f32": 24, "f32_f16store": 12, "f32_bf16store": 12}
 PMC_TRAFFIC = {
     "bytes_per_launch": 216.2e6 + 203.2e6,
     "fetch_bytes": 216.2e6, "write_bytes": 203.2e6,
+    "valu_lane_ops_per_cell": 309.0,
     "nx": 4096, "ny": 4096,
     "sources": {
         "fvna_device.hpp": "36224bdec71b2149af2a36c7e561432dc6c8d97c03d0f968f7e439323ef7115c",
         "fvna_runtime.hip": "81331248debaae07efbe8311f94b596b7ab0a8c598f93549c7c276d4e917e5ec",
     },
 }
+
+
+# Vector-ALU rate of the chip counted as the profile counts SQ_INSTS_VALU:
+# one wave64 instruction per CU per cycle = 256 CUs x 64 lanes x 2.4 GHz.
+VALU_PEAK_LANE_OPS = 256 * 64 * 2.4e9
+
+
+def measured_valu(nx, ny, kernel_s):
+    """VALU lane-ops per cell-update of the profiled kernel (SQ_INSTS_VALU x 64
+    / cells) and the rate they run at in the live launch, against the chip's
+    non-packed vector rate; None if the kernel sources or grid differ from the
+    profiled ones."""
+    if measured_traffic(nx, ny) is None:
+        return None
+    ops = PMC_TRAFFIC["valu_lane_ops_per_cell"]
+    rate = ops * nx * ny / kernel_s
+    return {"lane_ops_per_cell": ops, "achieved": round(rate / 1e12, 2), "peak": round(VALU_PEAK_LANE_OPS / 1e12, 2),
+            "unit": "T lane-ops/s", "frac": round(rate / VALU_PEAK_LANE_OPS, 4)}
 
 
 def measured_traffic(nx, ny):
@@ -272,7 +291,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(w["nx"], w["ny"]),
                      "kernel": "k_step<float,float,0>", "kernel_ms": round(ms_k, 4),
-                     "bytes_per_launch": BYTES_PER_CELL["f32"] * cells},
+                     "bytes_per_launch": BYTES_PER_CELL["f32"] * cells,
+                     "valu": measured_valu(w["nx"], w["ny"], ms_k * 1e-3)},
         "wall_s": round(r32["wall_s"], 4),
         "nu_mean": r32["nu_mean"], "nu_std": r32["nu_std"], "rejected": r32["rejected"],
     }
