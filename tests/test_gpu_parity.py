@@ -378,3 +378,36 @@ def test_oblique_taylor_all_sides_vs_oracle(orc, theta):
     _say(f"  max rel err {err:.3e}")
     assert err <= 1e-10
     sim.fvna_destroy()
+
+
+def test_window_and_recorder_refuse_bad_arguments():
+    """fvna_step_window, fvna_shift and fvna_set_recorder return
+    FVNA_E_INVALID for out-of-range arguments and sides that cannot move,
+    and leave the context usable."""
+    from paper_1311_3004_amd import fvna
+    import torch
+    w = pulse_workload(70, 40, ("extrap0", "extrap0", "reflect", "extrap0"), seed=31)
+    _say("case: bad arguments of the window and the recorder")
+    _, _, sim = run_gpu(w, 2, "f64")
+    st = fvna.fvna_window_state(0, 0)
+    for win in (fvna.fvna_window(0.0, 0, 4), fvna.fvna_window(0.0, 4, 0), fvna.fvna_window(float("nan"), 4, 4)):
+        with pytest.raises(fvna.FvnaError):
+            sim.fvna_step_window(win, st, 3)
+    with pytest.raises(fvna.FvnaError):
+        sim.fvna_step_window(fvna.fvna_window(0.0, 4, 4), fvna.fvna_window_state(0, 4), 3)
+    with pytest.raises(fvna.FvnaError):
+        sim.fvna_step_window(fvna.fvna_window(0.0, 4, 4), fvna.fvna_window_state(-1, 0), 3)
+    buf = torch.full((70,), -float("inf"), dtype=torch.float64, device="cuda:0")
+    for row, path in ((40, 70), (-1, 70), (0, 0)):
+        with pytest.raises(fvna.FvnaError):
+            sim.fvna_set_recorder(row, -1, path, buf)
+    with pytest.raises(fvna.FvnaError):
+        sim.fvna_set_recorder(0, -2, 70, buf)
+    sim.fvna_step_window(fvna.fvna_window(0.0, 4, 4), st, 5)     # still usable
+    assert sim.fvna_get_stats()["steps"] == 7
+    sim.fvna_destroy()
+    wt = pulse_workload(64, 40, ("periodic", "periodic", "extrap0", "extrap0"), seed=32)
+    _, _, sp = run_gpu(wt, 1, "f64")
+    with pytest.raises(fvna.FvnaError):
+        sp.fvna_step_window(fvna.fvna_window(0.0, 4, 4), fvna.fvna_window_state(0, 0), 3)
+    sp.fvna_destroy()
