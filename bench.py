@@ -173,8 +173,9 @@ def main():
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the slab decomposition it would use is described in DESIGN.md).", file=sys.stderr)
+        print("bench.py runs on one GPU only: there is no multi-GPU path (a large domain would "
+              "shard as slabs along x1 with a 3-cell halo exchange and one max-reduction of the "
+              "wave speed per step).", file=sys.stderr)
         sys.exit(2)
 
     import torch

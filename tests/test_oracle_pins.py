@@ -507,11 +507,13 @@ def test_exact_viscous_shock_profile_second_order(orc):
 
 
 def test_travelling_speed_matches_rankine_hugoniot():
-    """The speed formula, checked against the survey's worked value and against
-    the jump conditions written out independently."""
+    """The speed formula, checked against the closed form that the jump
+    conditions give for the symmetric jump R = +-a into still medium,
+    V = (1 - 2a/(1 + a)^2)^(-1/2) = 1.0029959 at a = 3e-3, and against the
+    jump conditions written out independently."""
     beta, a = 4.0, 3e-3
     V, _, _ = travelling_profile(beta, 0.04, a, np.array([0.0]))
-    assert abs(V - 1.00300) < 5e-6
+    assert abs(V - (1.0 - 2 * a / (1 + a) ** 2) ** -0.5) < 1e-12
     RL, RR = a, -a
     ML = V * (RL - RR)
     uL = ML / (1 + RL)
