@@ -405,5 +405,7 @@ def sim_from_workload(w, device="cuda:0", precision=None, **over):
         s.fvna_set_taylor(t["amplitude_pa"], t.get("x0_m", 0.0), t.get("angle", 0.0))
     s.fvna_set_state(*w["state"])
     if w.get("t0", 0.0) != 0.0:
-        s.fvna_set_clock(w["t0"], 0.0)
+        # keep a first step given in the parameters (fvna_set_clock recomputes
+        # it from the state when dt_next <= 0)
+        s.fvna_set_clock(w["t0"], p.dt0 if p.dt0 > 0 else 0.0)
     return s
