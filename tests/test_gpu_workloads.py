@@ -352,3 +352,34 @@ def test_recorder_matches_sampling_every_step(window_wl):
     n = min(len(th), len(td))
     assert abs(len(th) - len(td)) <= (0 if window_wl is None else 1) and n > 100
     assert np.array_equal(th[:n], td[:n]) and np.array_equal(prh[:n], prd[:n])
+
+
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-10), ("f32", 2e-6)])
+def test_batched_members_vs_oracle(precision, tol):
+    """The batch of 64 uneven simulations in the benchmark's launch
+    configuration (library default tile height), 3 adaptive steps; the
+    smallest, a middle and the largest member against the oracle run on that
+    member alone (each with its own medium and time step)."""
+    import oracle as orc
+    from paper_1311_3004_amd import fvna, inputs
+    sims = inputs.c4_batch()
+    plist = [fvna.make_params(x["nx"], x["ny"], x["dx"], x["medium"], bc=x["bc"], precision=precision)
+             for x in sims]
+    _say(f"case: batch of {len(sims)} {precision}, 3 steps, members vs oracle")
+    B = fvna.Batch(plist)
+    for k, x in enumerate(sims):
+        B.fvna_batch_set_state(k, *x["state"])
+    B.fvna_batch_step(3)
+    B.fvna_batch_sync()
+    order = sorted(range(len(sims)), key=lambda k: sims[k]["nx"] * sims[k]["ny"])
+    for k in (order[0], order[len(order) // 2], order[-1]):
+        x = sims[k]
+        med = x["medium"]
+        rp, mx, my = B.fvna_batch_get_state(k)
+        g = (rp / med["rho0"], mx / (med["rho0"] * med["c0"]), my / (med["rho0"] * med["c0"]))
+        o, info = run_oracle(orc, x, 3)
+        assert info["status"] == 0 and B.fvna_batch_get_stats(k)["steps"] == 3
+        err = max_rel(g, o)
+        _say(f"  member {k} {x['nx']}x{x['ny']}: max rel err {err:.3e}")
+        assert err <= tol
+    B.fvna_batch_destroy()
