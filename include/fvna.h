@@ -63,7 +63,11 @@ typedef enum { FVNA_CARTESIAN = 0, FVNA_AXISYMMETRIC = 1 } fvna_geometry;
 
 /* Arithmetic and storage precision of the step.  FP32 and the FP16/BF16
  * storage variants compute in FP32; the half-width variants store each field
- * as field/scale rounded to nearest-even (store_scale below). */
+ * as field/scale rounded to nearest-even (store_scale below): with v the field
+ * in FP32 and inv = 1/scale rounded to FP32, FP16 rounds the exact product
+ * v * inv once (a fused multiply-convert; a zero is stored as +0), BF16 rounds
+ * v * inv to FP32 and then to BF16.  Loads return the stored value times scale
+ * in FP32. */
 typedef enum { FVNA_F64 = 0, FVNA_F32 = 1, FVNA_F32_F16STORE = 2, FVNA_F32_BF16STORE = 3 } fvna_precision;
 
 /* Boundary kinds (ghost cells), per side: 0 = x-, 1 = x+, 2 = y-, 3 = y+.

@@ -411,3 +411,57 @@ def test_window_and_recorder_refuse_bad_arguments():
     with pytest.raises(fvna.FvnaError):
         sp.fvna_step_window(fvna.fvna_window(0.0, 4, 4), fvna.fvna_window_state(0, 0), 3)
     sp.fvna_destroy()
+
+
+def _to_bf16_rne(x32):
+    """float32 -> bfloat16 (kept in a float32), round to nearest even."""
+    b = np.asarray(x32, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    b = (b + 0x7FFF + ((b >> 16) & 1)) & 0xFFFF0000
+    return b.astype(np.uint32).view(np.float32)
+
+
+@pytest.mark.parametrize("precision", ["f32_f16store", "f32_bf16store"])
+def test_storage_codec_rounds_to_nearest_even(precision):
+    """Half-width storage: a value v (FP32) is stored as v * inv (inv = 1/scale
+    in FP32) rounded to nearest even -- FP16 from the exact product in one
+    rounding (the compiler fuses the multiply into the conversion, which also
+    stores a zero as +0), BF16 from the FP32 product -- and loaded as that
+    times scale (FP32).  On exact ties (odd multiples of half an ulp), values in
+    the FP16 subnormal range, +-0, the largest finite magnitudes and a scale
+    that is not a power of two, set_state -> get_state must give exactly
+    numpy's IEEE rounding of the same operations.  rho0 and c0 are powers of
+    two here, so the unit conversions are exact; no step is taken (most of
+    these states are far outside the hyperbolic region)."""
+    from paper_1311_3004_amd import fvna
+    med = {"c0": 1024.0, "rho0": 1024.0, "beta": 3.5, "delta": 4e-6}
+    scales = (2.0 ** -8, 2.0 ** -6, 3.0e-3)
+    half = precision == "f32_f16store"
+    ulp = 2.0 ** -10 if half else 2.0 ** -7
+    k = np.arange(-300, 300)
+    ties = 1.0 + (2 * k + 1) * (ulp / 2)                       # exactly halfway between neighbours
+    extra = [0.0, -0.0, 1e-5, -3.3e-6, 2.0 ** -20, 6.1e-5, 60000.0, -65000.0] if half else \
+            [0.0, -0.0, 1e-30, -3.3e-20, 1e30, -2.5e35, 3.0e38 / 1e3]
+    base = np.concatenate([ties, -ties * 0.75, np.array(extra), np.linspace(-3, 3, 400)])
+    nx, ny = 64, 40
+    vals = np.resize(base, nx * ny).reshape(ny, nx)
+    # a given first step: no dry pass over these (unphysical) values
+    s = fvna.Sim(fvna.make_params(nx, ny, 1e-4, med, precision=precision, store_scale=scales, dt0=1e-9))
+    denom = (med["rho0"], med["rho0"] * med["c0"], med["rho0"] * med["c0"])
+    fields = [vals * scales[f] * denom[f] for f in range(3)]
+    fields[1] = np.roll(fields[1], 7)
+    fields[2] = -fields[2]
+    _say(f"case: storage codec {precision}")
+    s.fvna_set_state(*fields)
+    out = s.fvna_get_state()
+    for f in range(3):
+        v32 = np.float32(fields[f] / denom[f])
+        inv32 = np.float32(1.0 / scales[f])
+        if half:   # the exact product (24 x 24 bits fit a double), rounded once; 0 -> +0
+            q = (v32.astype(np.float64) * np.float64(inv32)).astype(np.float16).astype(np.float32)
+            q = np.where(q == 0, np.float32(0.0), q)
+        else:
+            q = _to_bf16_rne((v32 * inv32).astype(np.float32))
+        want = (q * np.float32(scales[f])).astype(np.float32).astype(np.float64) * denom[f]
+        assert np.array_equal(out[f], want), f
+        assert np.array_equal(np.signbit(out[f]), np.signbit(want)), f
+    s.fvna_destroy()
