@@ -28,7 +28,10 @@
  *
  * Readings of points the paper leaves open are stated where they are used.
  * Parity status of each function is stated in its comment; the pins that fix
- * each one live in the test-suite.
+ * each one live in the test-suite.  Parity unpinned: the transverse momentum
+ * -r g/h of the focused source's ghost cells (set_ghost), which enters the
+ * interior only through the shear wave at the flow speed and changes no
+ * observable enough to check; it is compared with the HIP path only.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -465,7 +468,9 @@ static void source_step(const orc_params *p, double dt, field_t *in, field_t *ou
  * interior cells, once before and once after the x2 sweep (the sweep that
  * carries the radial flux): applied only after both sweeps the split step is
  * unstable near the axis above CFL ~0.8, applied symmetrically around the x2
- * sweep it is stable up to CFL 1 and second order in time. */
+ * sweep it is stable up to CFL 1 and second order in time.  Pinned by the
+ * exact Bessel modes (the linear terms) and by a steady radial source flow
+ * with axial drift (the quadratic terms -u v/r, -v^2/r). */
 static void geometric_half_step(const orc_params *p, double h, field_t *f)
 {
     for (int j = 0; j < f->ny; j++) {

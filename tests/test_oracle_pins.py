@@ -677,3 +677,92 @@ def test_analytic_y_sides_step_the_exact_plane_wave_like_periodic_rows(orc):
         for a, b in ((Ra, Rp), (Ma, Mp), (Na, Np)):
             assert np.array_equal(a, b)
         assert np.all(Na == 0.0) and np.max(np.abs(Ra - R)) > 1e-3 * amp
+
+
+# -- Axisymmetric hoop terms: steady radial source flow --------------------------
+
+def _steady_radial_R(beta, C, rhat):
+    """R(r) of the steady inviscid radial flow N = C/r, u v r = K (r in units
+    of the domain height): the radial momentum balance of the model in
+    cylindrical coordinates, d(v^2 + phi(R))/dr = -v^2/r with v = C/(r(1+R)),
+    phi(R) = R + (beta - 1) R^2, solved for R' and integrated with RK4 from
+    R(1/2) = 0 on a fine grid."""
+    def f(r, R):
+        v = C / (r * (1 + R))
+        return (v * v / r) / (1 + 2 * (beta - 1) * R - 2 * v * v / (1 + R))
+    grid = np.linspace(0.05, 1.0, 19001)
+    R = np.zeros_like(grid)
+    i0 = np.searchsorted(grid, 0.5)
+    for sgn in (1, -1):
+        for i in (range(i0, len(grid) - 1) if sgn > 0 else range(i0, 0, -1)):
+            j = i + sgn
+            h, r, y = grid[j] - grid[i], grid[i], R[i]
+            k1 = f(r, y)
+            k2 = f(r + h / 2, y + h / 2 * k1)
+            k3 = f(r + h / 2, y + h / 2 * k2)
+            k4 = f(r + h, y + h * k3)
+            R[j] = y + h / 6 * (k1 + 2 * k2 + 2 * k3 + k4)
+    return np.interp(rhat, grid, R)
+
+
+def test_axisymmetric_hoop_terms_keep_a_steady_radial_flow(orc):
+    """A steady, z-independent, inviscid flow in (z, r): mass gives r N = C,
+    axial momentum (1/r) d(r u v)/dr = 0 gives u v r = K, radial momentum
+    d(v^2 + phi)/dr + v^2/r = 0 fixes R(r) -- the balances in which the
+    geometric terms -N/r, -u v/r and -v^2/r of reading R5 appear.  Started
+    from this state (blended to rest near the axis, where the flow is
+    singular) the scheme may move it only by its truncation error: in the band
+    0.35 < r < 0.65, which neither the blend nor the outer side reaches by
+    t = 0.12, the error in R, M and N converges at second order under
+    refinement (64, 128, 256 rows).  A missing or sign-flipped -v^2/r or a
+    missing -u v/r leaves an O(1) residual there and no convergence."""
+    beta, C, K, T = 4.8, 2e-3, 1e-5, 0.12
+    errs = []
+    for n in (64, 128, 256):
+        rj = (np.arange(n) + 0.5) / n
+        R = _steady_radial_R(beta, C, rj)
+        s = np.clip((rj - 0.05) / 0.1, 0.0, 1.0)
+        N = C / rj * s * s * (3 - 2 * s)
+        M = K * (1 + R) ** 2 / C
+        Q = [np.tile(a[:, None], (1, 4)) for a in (R, M, N)]
+        p = orc.make_params(4, n, beta, 0.0, bc=("periodic", "periodic", "extrap0", "extrap0"),
+                            geometry="axisym")
+        t, dt = 0.0, 0.0
+        while t < T * n:
+            R1, M1, N1, info = orc.run(p, *Q, 1, t=t, dt=dt)
+            assert info["status"] == 0
+            Q, t, dt = [R1, M1, N1], info["t"], info["dt_next"]
+        band = (rj > 0.35) & (rj < 0.65)
+        scales = (np.ptp(R[band]), np.max(np.abs(M[band])), np.max(np.abs(N[band])))
+        errs.append([np.max(np.abs(q[band, 0] - e[band])) / sc for q, e, sc in zip(Q, (R, M, N), scales)])
+    errs = np.array(errs)
+    orders = np.log2(errs[:-1] / errs[1:])
+    assert np.all(orders > 1.6), (errs, orders)
+    assert errs[-1][0] < 0.05 and errs[-1][1] < 1e-5 and errs[-1][2] < 1e-4, errs
+
+
+def test_focused_packet_focuses_near_f(orc):
+    """The focusing delay of eq. hifuBC, tau = t + r^2/(2F): a small-amplitude
+    packet from an aperture of 8 wavelengths with F = 20 wavelengths (10 cells
+    per wavelength, inviscid) must peak on the axis a little before F (the
+    focal shift of a finite aperture) with a gain near the 2-D estimate
+    sqrt(2 a^2 / (lambda F)) = 2.5.  A delay of the wrong sign does not focus
+    at all (peak at the source, gain < 1); twice the delay focuses at F/2."""
+    eta, F_wl, a_wl, A = 10.0, 20.0, 8.0, 1e-6
+    f = 1.0 / eta
+    nx, ny = int(30 * eta), int((a_wl + 4) * eta)
+    p = orc.make_params(nx, ny, 4.8, 0.0, bc=("source", "extrap0", "reflect", "extrap0"),
+                        source={"amp": A, "freq": f, "focal": F_wl * eta, "aperture": a_wl * eta,
+                                "envelope": "packet", "packet_cycles": 4.0})
+    Q = [np.zeros((ny, nx)) for _ in range(3)]
+    t, dt = -6.0 / f, 0.0
+    pmax = np.zeros(nx)
+    while t < (30 + 6.5) / f:
+        R, M, N, info = orc.run(p, *Q, 1, t=t, dt=dt)
+        assert info["status"] == 0
+        Q, t, dt = [R, M, N], info["t"], info["dt_next"]
+        np.maximum(pmax, R[0], out=pmax)
+    k = int(np.argmax(pmax))
+    x_over_f, gain = (k + 0.5) / eta / F_wl, pmax[k] / A
+    assert 0.75 < x_over_f < 0.98, x_over_f
+    assert 1.8 < gain < 2.6, gain
