@@ -32,16 +32,17 @@ BYTES_PER_CELL = {"f64": 48, "f32": 24, "f32_f16store": 12, "f32_bf16store": 12}
 # HBM bytes per launch of the FP32 step kernel on this workload, from two
 # rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE), each scaled by what the
 # same counter reads for a plain 1 GiB device copy (fetch x2.000, write x1.000);
-# profiles/k_step_f32_gaussian4096.md.  Valid only for the kernel sources
-# whose SHA-256 is recorded here: any other source reports traffic null.
+# profiles/k_step_f32_gaussian4096.md.  Valid only for the kernel sources and
+# build flags whose SHA-256 is recorded here: anything else reports null.
 PMC_TRAFFIC = {
-    "bytes_per_launch": 216.2e6 + 203.2e6,
-    "fetch_bytes": 216.2e6, "write_bytes": 203.2e6,
-    "valu_lane_ops_per_cell": 309.0,
+    "bytes_per_launch": 216.1e6 + 204.4e6,
+    "fetch_bytes": 216.1e6, "write_bytes": 204.4e6,
+    "valu_lane_ops_per_cell": 308.0,
     "nx": 4096, "ny": 4096,
     "sources": {
         "fvna_device.hpp": "36224bdec71b2149af2a36c7e561432dc6c8d97c03d0f968f7e439323ef7115c",
         "fvna_runtime.hip": "81331248debaae07efbe8311f94b596b7ab0a8c598f93549c7c276d4e917e5ec",
+        "build.py": "1709860880cb190303f24f18d1fde1d9184d0402975a6b07f4af871ebecdc2f1",
     },
 }
 
@@ -70,7 +71,8 @@ def measured_traffic(nx, ny):
     if (nx, ny) != (PMC_TRAFFIC["nx"], PMC_TRAFFIC["ny"]):
         return None
     for name, digest in PMC_TRAFFIC["sources"].items():
-        path = os.path.join(ROOT, "paper_1311_3004_amd", "csrc", name)
+        sub = () if name == "build.py" else ("csrc",)
+        path = os.path.join(ROOT, "paper_1311_3004_amd", *sub, name)
         with open(path, "rb") as f:
             if hashlib.sha256(f.read()).hexdigest() != digest:
                 return None
