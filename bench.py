@@ -141,6 +141,42 @@ def other_configs(fvna, inputs, steps):
     return out
 
 
+def three_d(n=256, steps=20):
+    """The 3-D step (first version: one kernel per sweep and one for the
+    source, the step decided on the host) on an n^3 FP32 Gaussian pulse
+    (sigma 8 cells, 2 MPa, 0.5% noise, seed 5), extrapolating sides: whole
+    steps per second (host clock, one synchronisation per step) and the mean
+    duration of the four kernels of one step (HIP events) against 32 B per
+    cell-update (read and write of four FP32 fields)."""
+    import time
+    import numpy as np
+    from paper_1311_3004_amd import fvna3d as f3
+    from paper_1311_3004_amd.inputs import WATER
+    med = dict(WATER)
+    rng = np.random.default_rng(5)
+    c = (np.arange(n) + 0.5 - n / 2) ** 2
+    a = 2e6 / (med["rho0"] * med["c0"] ** 2)
+    R = a * np.exp(-(c[:, None, None] + c[None, :, None] + c[None, None, :]) / (2 * 8.0 ** 2))
+    R += 0.005 * a * rng.uniform(-1, 1, R.shape)
+    Z = np.zeros_like(R)
+    s = f3.Sim3(f3.make_params(n, n, n, 1e-4, med, precision="f32"))
+    s.fvna3_set_state(R * med["rho0"], Z, Z, Z)
+    del R, Z
+    s.fvna3_step(3)
+    t0 = time.perf_counter()
+    s.fvna3_step(steps)
+    wall = time.perf_counter() - t0
+    ms = s.fvna3_time_step_kernels(10)
+    cells = n ** 3
+    gbs = 32 * cells / (ms * 1e-3) / 1e9
+    s.fvna3_destroy()
+    log(f"[bench] 3-D {n}^3 fp32: {cells * steps / wall / 1e6:.1f} Mcell/s, step kernels {ms:.3f} ms = {gbs:.0f} GB/s")
+    return {"workload": f"gaussian-pulse {n}^3 fp32", "value": round(cells * steps / wall / 1e6, 1),
+            "unit": "Mcell-updates/s", "steps": steps, "step_kernels_ms": round(ms, 4),
+            "kernel_rate": round(cells / (ms * 1e-3) / 1e6, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+            "bytes_per_cell_update": 32}
+
+
 def cpu_baseline(w, steps):
     """FP64 oracle on the host: `steps` steps of the same workload, full grid."""
     import oracle
@@ -167,6 +203,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-other", action="store_true", help="skip the axisymmetric configs")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 3-D leg")
     ap.add_argument("--other-steps", type=int, default=200)
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=3)
@@ -274,6 +311,8 @@ def main():
 
     if not args.no_other:
         extra["other_configs"] = other_configs(fvna, inputs, args.other_steps)
+    if not args.no_3d:
+        extra["three_d"] = three_d()
 
     out = {
         "metric": "Mcell-updates/s and % HBM roofline, FP32/batched vs FP64 at stated error",

@@ -100,3 +100,34 @@ def test_struct_layouts_match_the_header(fv, tmp_path):
         assert int(got[name]) == ctypes.sizeof(cls), name
         for field, _ in cls._fields_:
             assert int(got[f"{name}.{field}"]) == getattr(cls, field).offset, f"{name}.{field}"
+
+
+def test_3d_library_exports_every_declared_symbol_and_matches_its_struct():
+    """libfvna3d.so exports every entry point include/fvna3d.h declares, and
+    the ctypes mirror of fvna3_params has the C compiler's layout."""
+    import subprocess
+    import tempfile
+    from paper_1311_3004_amd import build3d
+    if not os.path.exists(build3d.LIB):
+        build3d.build()
+    from paper_1311_3004_amd import fvna3d as f3
+    h3 = os.path.join(ROOT, "include", "fvna3d.h")
+    text = re.sub(r"/\*.*?\*/", "", open(h3).read(), flags=re.S)
+    names = sorted(set(re.findall(r"\b(fvna3_[a-z_]+)\s*\(", text)))
+    L = ctypes.CDLL(f3.LIB_PATH)
+    assert not [n for n in names if not hasattr(L, n)]
+    assert sorted(f3.EXPORTS) == names
+    with tempfile.TemporaryDirectory() as td:
+        lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{h3}"', "int main(void) {",
+                 '  printf("size %zu\\n", sizeof(fvna3_params));']
+        for field, _ in f3.fvna3_params._fields_:
+            lines.append(f'  printf("{field} %zu\\n", offsetof(fvna3_params, {field}));')
+        lines += ["  return 0;", "}"]
+        src = os.path.join(td, "l.c")
+        open(src, "w").write("\n".join(lines))
+        exe = os.path.join(td, "l")
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", exe, src], check=True)
+        got = dict(l.split() for l in subprocess.run([exe], capture_output=True, text=True, check=True).stdout.splitlines())
+    assert int(got["size"]) == ctypes.sizeof(f3.fvna3_params)
+    for field, _ in f3.fvna3_params._fields_:
+        assert int(got[field]) == getattr(f3.fvna3_params, field).offset, field

@@ -1,0 +1,71 @@
+"""The 3-D step through its C ABI against the 3-D FP64 oracle: a ragged grid
+with all three side kinds, a seeded pulse with momentum in every component,
+fixed and adaptive time steps, FP64 and FP32.  Tolerances relative to the
+peak |R|: FP64 1e-12 (fixed dt) / 1e-10 (adaptive), FP32 2e-6."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+MED = {"c0": 1500.0, "rho0": 1000.0, "beta": 3.5, "delta": 4.3e-6}
+DX = 1e-4
+BC = ("extrap0", "reflect", "periodic", "periodic", "reflect", "extrap0")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _state(nx, ny, nz, seed):
+    rng = np.random.default_rng(seed)
+    z, y, x = np.meshgrid(np.arange(nz) + 0.5, np.arange(ny) + 0.5, np.arange(nx) + 0.5, indexing="ij")
+    a = 2e6 / (MED["rho0"] * MED["c0"] ** 2)
+    R = a * np.exp(-((x - 0.45 * nx) ** 2 + (y - 0.5 * ny) ** 2 + (z - 0.4 * nz) ** 2) / (2 * 3.0 ** 2))
+    R = R + 0.01 * a * rng.uniform(-1, 1, R.shape)
+    M = [c * R for c in (0.3, -0.2, 0.25)]
+    return R, M
+
+
+def _run_pair(precision, steps, fixed, dt_cells=0.6, shape=(20, 14, 10), seed=3):
+    from paper_1311_3004_amd import fvna3d as f3
+    from oracle import oracle3d as o3
+    nx, ny, nz = shape
+    R, M = _state(nx, ny, nz, seed)
+    rho0, c0 = MED["rho0"], MED["c0"]
+    dt_si = dt_cells * DX / c0 if fixed else 0.0
+    p = f3.make_params(nx, ny, nz, DX, MED, bc=BC, precision=precision, fixed_dt=fixed, dt0=dt_si)
+    s = f3.Sim3(p)
+    s.fvna3_set_state(R * rho0, *[m * rho0 * c0 for m in M])
+    s.fvna3_step(steps)
+    g = s.fvna3_get_state()
+    st = s.fvna3_get_stats()
+    s.fvna3_destroy()
+    g = (g[0] / rho0,) + tuple(m / (rho0 * c0) for m in g[1:])
+    po = o3.make_params(nx, ny, nz, MED["beta"], MED["delta"] / (c0 * DX), bc=BC, fixed_dt=fixed)
+    o, info = o3.run(po, [R] + M, steps, dt=dt_cells if fixed else 0.0)
+    assert info["status"] == 0 and st["steps"] == steps
+    err = max(np.max(np.abs(a - b)) for a, b in zip(g, o)) / np.max(np.abs(o[0]))
+    return err, st, info
+
+
+@pytest.mark.parametrize("precision,fixed,tol", [("f64", True, 1e-12), ("f64", False, 1e-10), ("f32", True, 2e-6)])
+def test_3d_step_vs_oracle(precision, fixed, tol):
+    _say(f"case: 3-D 20x14x10 {precision} {'fixed' if fixed else 'adaptive'} dt, 12 steps")
+    err, st, info = _run_pair(precision, 12, fixed)
+    _say(f"  max rel err {err:.3e}")
+    assert err <= tol
+    if not fixed:
+        assert abs(st["t"] * MED["c0"] / DX - info["t"]) <= 1e-12 * info["t"]
+
+
+def test_3d_refuses_bad_parameters():
+    from paper_1311_3004_amd import fvna, fvna3d as f3
+    for bc in (("taylor",) * 6, ("periodic", "extrap0") + ("extrap0",) * 4):
+        p = f3.make_params(8, 8, 8, DX, MED, bc=bc)
+        with pytest.raises(fvna.FvnaError):
+            f3.Sim3(p)
+    with pytest.raises(fvna.FvnaError):
+        f3.Sim3(f3.make_params(3, 8, 8, DX, MED))
