@@ -69,3 +69,22 @@ def test_3d_refuses_bad_parameters():
             f3.Sim3(p)
     with pytest.raises(fvna.FvnaError):
         f3.Sim3(f3.make_params(3, 8, 8, DX, MED))
+
+
+def test_3d_reports_a_nonhyperbolic_state():
+    """A state outside the model's hyperbolic region (velocity twice the
+    sound speed) is refused when the first step is computed from it, with
+    FVNA_E_NONHYPERBOLIC; the context stays usable for a valid state."""
+    from paper_1311_3004_amd import fvna, fvna3d as f3
+    nx, ny, nz = 12, 10, 8
+    s = f3.Sim3(f3.make_params(nx, ny, nz, DX, MED, bc=BC))
+    Z = np.zeros((nz, ny, nx))
+    R = Z + 0.01
+    with pytest.raises(fvna.FvnaError) as e:
+        s.fvna3_set_state(R * MED["rho0"], (1 + R) * 2.0 * MED["rho0"] * MED["c0"], Z, Z)
+    assert e.value.status == fvna.E_NONHYPERBOLIC
+    R, M = _state(nx, ny, nz, 11)
+    s.fvna3_set_state(R * MED["rho0"], *[m * MED["rho0"] * MED["c0"] for m in M])
+    s.fvna3_step(3)
+    assert s.fvna3_get_stats()["steps"] == 3
+    s.fvna3_destroy()
