@@ -86,6 +86,9 @@ def lib():
         L.orc_taylor_value.argtypes = [ctypes.POINTER(Params), d, d, d, dp]
         L.orc_source_g.restype = d
         L.orc_source_g.argtypes = [ctypes.POINTER(Params), d, d]
+        L.orc_ghost.restype = ctypes.c_int
+        L.orc_ghost.argtypes = [ctypes.POINTER(Params), dp, dp, dp, d, ctypes.c_int, ctypes.c_int,
+                                ctypes.c_int, ctypes.c_int, dp]
         _lib = L
     return _lib
 
@@ -218,8 +221,23 @@ def source_g(p, r, t):
     return lib().orc_source_g(ctypes.byref(p), float(r), float(t))
 
 
+def ghost(p, R, M, N, t, side, gi, gj, layer):
+    """(R, M, N) of ghost cell (gi, gj), layer `layer` of side `side` (0: x-, 1: x+,
+    2: y-, 3: y+) at time t, by that side's boundary rule from the interior state."""
+    R = np.ascontiguousarray(R, dtype=np.float64)
+    M = np.ascontiguousarray(M, dtype=np.float64)
+    N = np.ascontiguousarray(N, dtype=np.float64)
+    assert R.shape == (p.ny, p.nx) and M.shape == R.shape and N.shape == R.shape
+    q = np.zeros(3)
+    e = lib().orc_ghost(ctypes.byref(p), _ptr(R), _ptr(M), _ptr(N), float(t), int(side), int(gi),
+                        int(gj), int(layer), _ptr(q))
+    if e != OK:
+        raise ValueError(f"orc_ghost: error {e} for side {side}, cell ({gi}, {gj}), layer {layer}")
+    return q
+
+
 __all__ = ["build", "lib", "roe", "mc", "flux", "make_params", "make_params_si", "run",
-           "dry_smax", "taylor_value", "source_g", "BC", "GEOM", "Params", "Stats"]
+           "dry_smax", "taylor_value", "source_g", "ghost", "BC", "GEOM", "Params", "Stats"]
 
 
 def shift(R, M, N, ncols):

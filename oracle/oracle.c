@@ -27,11 +27,10 @@
  *   around the x2 sweep (geometric_half_step).
  *
  * Readings of points the paper leaves open are stated where they are used.
- * Parity status of each function is stated in its comment; the pins that fix
- * each one live in the test-suite.  Parity unpinned: the transverse momentum
- * -r g/h of the focused source's ghost cells (set_ghost), which enters the
- * interior only through the shear wave at the flow speed and changes no
- * observable enough to check; it is compared with the HIP path only.
+ * The pins that fix each function live in the test-suite; every side rule of
+ * set_ghost is checked cell by cell through orc_ghost (the focused source's
+ * momentum against the direction to the focus), and the reject-and-redo rule
+ * of orc_run against single attempts at the two time steps involved.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -715,6 +714,38 @@ int orc_run(const orc_params *p, double *R, double *M, double *N, long nsteps,
     st->status = e;
     st->status_step = e ? accepted : 0;
     return e;
+}
+
+/* Ghost cell (gi, gj) of ghost layer `layer` (1 = adjacent) on `side` (0: x-,
+ * 1: x+, 2: y-, 3: y+) at time t, filled by the boundary rule of that side
+ * from the interior state (R, M, N: row-major [ny][nx]) into q = (R, M, N).
+ * Exported so that the pins can check every side rule cell by cell.  The
+ * cell must lie on that side's ghost frame: gi = -layer (side 0) or
+ * nx - 1 + layer (side 1) with 0 <= gj < ny, gj = -layer (side 2) or
+ * ny - 1 + layer (side 3) with 0 <= gi < nx; else ORC_E_INVALID. */
+int orc_ghost(const orc_params *p, const double *R, const double *M, const double *N, double t,
+              int side, int gi, int gj, int layer, double q[3])
+{
+    if (check_params(p)) return ORC_E_INVALID;
+    if (side < 0 || side > 3 || layer < 1 || layer > GH) return ORC_E_INVALID;
+    int nx = p->nx, ny = p->ny;
+    int ok = (side == 0 && gi == -layer && gj >= 0 && gj < ny) ||
+             (side == 1 && gi == nx - 1 + layer && gj >= 0 && gj < ny) ||
+             (side == 2 && gj == -layer && gi >= 0 && gi < nx) ||
+             (side == 3 && gj == ny - 1 + layer && gi >= 0 && gi < nx);
+    if (!ok) return ORC_E_INVALID;
+    field_t g;
+    if (field_alloc(&g, nx, ny)) { field_free(&g); return ORC_E_NOMEM; }
+    for (int j = 0; j < ny; j++)
+        for (int i = 0; i < nx; i++) {
+            size_t d = idx(&g, i, j), s = (size_t)j * nx + i;
+            g.R[d] = R[s]; g.M[d] = M[s]; g.N[d] = N[s];
+        }
+    set_ghost(p, t, &g, side, gi, gj, layer);
+    size_t d = idx(&g, gi, gj);
+    q[0] = g.R[d]; q[1] = g.M[d]; q[2] = g.N[d];
+    field_free(&g);
+    return ORC_OK;
 }
 
 /* Ghost value of the analytic Taylor profile and of the focused source, for

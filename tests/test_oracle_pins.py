@@ -766,3 +766,59 @@ def test_focused_packet_focuses_near_f(orc):
     x_over_f, gain = (k + 0.5) / eta / F_wl, pmax[k] / A
     assert 0.75 < x_over_f < 0.98, x_over_f
     assert 1.8 < gain < 2.6, gain
+
+
+# ---------------------------------------------------------------------------
+# CFL control: rejection and redo (opening of Sec. 4; reading R4).  A step whose
+# CFL number exceeds nu_max is discarded and redone from the same Q^n with
+# dt nu_W / nu.  Pinned against single attempts at the two time steps: the
+# rejected-then-redone run must equal, bit for bit, one fresh attempt at the
+# redone step from Q^n.
+# ---------------------------------------------------------------------------
+
+def _redo_case(orc):
+    from common import dimless_state, oracle_params, pulse_workload
+    w = pulse_workload(40, 32, ("extrap0", "extrap0", "reflect", "extrap0"), seed=11)
+    p = oracle_params(orc, w)
+    pf = oracle_params(orc, w, fixed_dt=True)
+    R, M, N = dimless_state(w)
+    return p, pf, R, M, N
+
+
+def test_rejected_step_is_redone_from_the_same_state(orc):
+    p, pf, R, M, N = _redo_case(orc)
+    assert p.cfl_max == 1.0 and p.cfl_target == 0.9
+    dt_bad = 3.0 * p.cfl_target / orc.dry_smax(p, R, M, N)
+    # the first attempt on its own (fixed dt: nu recorded, never rejected)
+    _, _, _, a1 = orc.run(pf, R, M, N, 1, dt=dt_bad)
+    nu1 = a1["nu_last"]
+    assert nu1 > p.cfl_max
+    dt_redo = dt_bad * p.cfl_target / nu1
+    # the adaptive run from dt_bad: one rejection, then the redo
+    Ra, Ma, Na, ia = orc.run(p, R, M, N, 1, dt=dt_bad)
+    assert ia["status"] == orc.OK and ia["rejected"] == 1 and ia["steps"] == 1
+    # one fresh attempt at dt_redo from the same Q^n
+    Rb, Mb, Nb, ib = orc.run(pf, R, M, N, 1, dt=dt_redo)
+    assert ib["nu_last"] <= p.cfl_max
+    for x, y in zip((Ra, Ma, Na), (Rb, Mb, Nb)):
+        assert np.array_equal(x, y)
+    assert ia["t"] == dt_redo
+    assert ia["nu_last"] == ib["nu_last"]
+    assert ia["dt_next"] == dt_redo * p.cfl_target / ib["nu_last"]
+    # the input is not the answer: the redone step did change the state
+    assert not np.array_equal(Ra, R)
+
+
+def test_no_retries_left_keeps_the_state(orc):
+    p, pf, R, M, N = _redo_case(orc)
+    p.max_retries = 0
+    dt_bad = 3.0 * p.cfl_target / orc.dry_smax(p, R, M, N)
+    R1, M1, N1, info = orc.run(p, R, M, N, 3, dt=dt_bad)
+    assert info["status"] == orc.E_RETRIES
+    assert info["steps"] == 0 and info["rejected"] == 1 and info["status_step"] == 0
+    for x, y in zip((R1, M1, N1), (R, M, N)):
+        assert np.array_equal(x, y)
+    # with one retry allowed the same run succeeds
+    p.max_retries = 1
+    _, _, _, info = orc.run(p, R, M, N, 3, dt=dt_bad)
+    assert info["status"] == orc.OK and info["steps"] == 3 and info["rejected"] == 1
