@@ -54,7 +54,7 @@ def build(force=False):
     """Compile oracle.c into liboracle.so with gcc (FP64, no FMA contraction)."""
     if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
         return _LIB
-    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
            "-o", _LIB, _SRC, "-lm"]
     subprocess.run(cmd, check=True)
     return _LIB
@@ -86,6 +86,10 @@ def lib():
         L.orc_taylor_value.argtypes = [ctypes.POINTER(Params), d, d, d, dp]
         L.orc_source_g.restype = d
         L.orc_source_g.argtypes = [ctypes.POINTER(Params), d, d]
+        L.orc_set_threads.restype = None
+        L.orc_set_threads.argtypes = [ctypes.c_int]
+        L.orc_get_threads.restype = ctypes.c_int
+        L.orc_get_threads.argtypes = []
         L.orc_ghost.restype = ctypes.c_int
         L.orc_ghost.argtypes = [ctypes.POINTER(Params), dp, dp, dp, d, ctypes.c_int, ctypes.c_int,
                                 ctypes.c_int, ctypes.c_int, dp]
@@ -221,6 +225,16 @@ def source_g(p, r, t):
     return lib().orc_source_g(ctypes.byref(p), float(r), float(t))
 
 
+def set_threads(n):
+    """Worker threads of the oracle's sweeps and source (OpenMP over rows; the
+    result is bitwise the same for every count).  Default 1."""
+    lib().orc_set_threads(int(n))
+
+
+def get_threads():
+    return lib().orc_get_threads()
+
+
 def ghost(p, R, M, N, t, side, gi, gj, layer):
     """(R, M, N) of ghost cell (gi, gj), layer `layer` of side `side` (0: x-, 1: x+,
     2: y-, 3: y+) at time t, by that side's boundary rule from the interior state."""
@@ -237,7 +251,7 @@ def ghost(p, R, M, N, t, side, gi, gj, layer):
 
 
 __all__ = ["build", "lib", "roe", "mc", "flux", "make_params", "make_params_si", "run",
-           "dry_smax", "taylor_value", "source_g", "ghost", "BC", "GEOM", "Params", "Stats"]
+           "dry_smax", "taylor_value", "source_g", "ghost", "set_threads", "get_threads", "BC", "GEOM", "Params", "Stats"]
 
 
 def shift(R, M, N, ncols):

@@ -10,6 +10,10 @@
  * benchmark, never by the product library.  It shares no code, header, table
  * or helper with the HIP path.  Compile with -ffp-contract=off (no FMA
  * contraction) so that every operation below rounds exactly as written.
+ * Serial by default; with -fopenmp and orc_set_threads(n) the rows of a sweep
+ * (columns of the x2 sweep) and of the source are shared among n threads,
+ * each row computed exactly as in the serial run, so the result is bitwise
+ * independent of n.
  *
  * Units.  Lengths are measured in cells (the reference length L of the
  * paper's renormalisation, Sec. 3 eq. renorm, is taken as the mesh spacing,
@@ -35,6 +39,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 enum { ORC_OK = 0, ORC_E_INVALID = 1, ORC_E_NOMEM = 2, ORC_E_NONHYPERBOLIC = 4,
        ORC_E_NONFINITE = 5, ORC_E_RETRIES = 6 };
@@ -422,17 +429,20 @@ static void fill_ghosts_y_q1(const orc_params *p, double t, field_t *g, int laye
  * Laplacian adds (1/r) d/dr of each velocity component and -v/r^2 to the
  * radial one.  The geometric (hoop) terms of the divergence are not part of
  * this step: see geometric_half_step. */
-static void source_step(const orc_params *p, double dt, field_t *in, field_t *out)
+static int source_step(const orc_params *p, double dt, field_t *in, field_t *out, int nt)
 {
     int nx = in->nx, ny = in->ny;
     size_t n = (size_t)in->pitch * (size_t)(ny + 2 * GH);
     double *u = malloc(n * sizeof(double));
     double *v = malloc(n * sizeof(double));
-    for (size_t k = 0; k < n; k++) {
+    if (!u || !v) { free(u); free(v); return ORC_E_NOMEM; }
+#pragma omp parallel for schedule(static) num_threads(nt)
+    for (long k = 0; k < (long)n; k++) {
         double q1 = 1.0 + in->R[k];
         u[k] = in->M[k] / q1;
         v[k] = in->N[k] / q1;
     }
+#pragma omp parallel for schedule(static) num_threads(nt)
     for (int j = 0; j < ny; j++)
         for (int i = 0; i < nx; i++) {
             size_t c = idx(in, i, j);
@@ -457,6 +467,7 @@ static void source_step(const orc_params *p, double dt, field_t *in, field_t *ou
         }
     free(u);
     free(v);
+    return ORC_OK;
 }
 
 /* Axisymmetric geometric terms (not in the paper; derived from eq.
@@ -470,8 +481,10 @@ static void source_step(const orc_params *p, double dt, field_t *in, field_t *ou
  * sweep it is stable up to CFL 1 and second order in time.  Pinned by the
  * exact Bessel modes (the linear terms) and by a steady radial source flow
  * with axial drift (the quadratic terms -u v/r, -v^2/r). */
-static void geometric_half_step(const orc_params *p, double h, field_t *f)
+static void geometric_half_step(const orc_params *p, double h, field_t *f, int nt)
 {
+    (void)p;
+#pragma omp parallel for schedule(static) num_threads(nt)
     for (int j = 0; j < f->ny; j++) {
         double r = j + 0.5;
         for (int i = 0; i < f->nx; i++) {
@@ -492,7 +505,34 @@ static void geometric_half_step(const orc_params *p, double h, field_t *f)
 /* Full step and driver.                                                     */
 /* ------------------------------------------------------------------------- */
 
-typedef struct { field_t a, b, c, d; double *lr, *ln, *lt, *or_, *on, *ot; iface_t *f; } work_t;
+/* Scratch of one worker: the line being swept and its interfaces, and that
+ * worker's share of the CFL maximum. */
+typedef struct {
+    double *lr, *ln, *lt, *or_, *on, *ot;
+    iface_t *f;
+    double smax;
+    int bad, err;
+    char pad[64];        /* keeps the workers' entries on separate cache lines */
+} line_t;
+
+typedef struct { field_t a, b, c, d; int nt; line_t *line; } work_t;
+
+/* Worker threads of the sweeps and the source (OpenMP over rows, or over
+ * columns for the x2 sweep).  Each row is computed by one thread with the
+ * same operations as in a serial run, and the per-thread CFL maxima are
+ * merged in thread order by the same rule, so the result does not depend on
+ * the thread count.  Default 1. */
+static int g_threads = 1;
+
+void orc_set_threads(int n) { g_threads = n > 0 ? n : 1; }
+int orc_get_threads(void)
+{
+#ifdef _OPENMP
+    return g_threads;
+#else
+    return 1;
+#endif
+}
 
 static int work_alloc(work_t *w, int nx, int ny)
 {
@@ -500,17 +540,57 @@ static int work_alloc(work_t *w, int nx, int ny)
     int e = field_alloc(&w->a, nx, ny) | field_alloc(&w->b, nx, ny) |
             field_alloc(&w->c, nx, ny) | field_alloc(&w->d, nx, ny);
     int m = (nx > ny ? nx : ny) + 2 * GH;
-    w->lr = malloc(sizeof(double) * m); w->ln = malloc(sizeof(double) * m); w->lt = malloc(sizeof(double) * m);
-    w->or_ = malloc(sizeof(double) * m); w->on = malloc(sizeof(double) * m); w->ot = malloc(sizeof(double) * m);
-    w->f = malloc(sizeof(iface_t) * (size_t)(m + 1));
-    if (e || !w->lr || !w->ln || !w->lt || !w->or_ || !w->on || !w->ot || !w->f) return ORC_E_NOMEM;
+    w->nt = orc_get_threads();
+    w->line = calloc((size_t)w->nt, sizeof(line_t));
+    if (e || !w->line) return ORC_E_NOMEM;
+    for (int k = 0; k < w->nt; k++) {
+        line_t *L = &w->line[k];
+        L->lr = malloc(sizeof(double) * m); L->ln = malloc(sizeof(double) * m); L->lt = malloc(sizeof(double) * m);
+        L->or_ = malloc(sizeof(double) * m); L->on = malloc(sizeof(double) * m); L->ot = malloc(sizeof(double) * m);
+        L->f = malloc(sizeof(iface_t) * (size_t)(m + 1));
+        if (!L->lr || !L->ln || !L->lt || !L->or_ || !L->on || !L->ot || !L->f) return ORC_E_NOMEM;
+    }
     return ORC_OK;
 }
 
 static void work_free(work_t *w)
 {
     field_free(&w->a); field_free(&w->b); field_free(&w->c); field_free(&w->d);
-    free(w->lr); free(w->ln); free(w->lt); free(w->or_); free(w->on); free(w->ot); free(w->f);
+    if (w->line)
+        for (int k = 0; k < w->nt; k++) {
+            line_t *L = &w->line[k];
+            free(L->lr); free(L->ln); free(L->lt); free(L->or_); free(L->on); free(L->ot); free(L->f);
+        }
+    free(w->line);
+}
+
+static int thread_id(void)
+{
+#ifdef _OPENMP
+    return omp_get_thread_num();
+#else
+    return 0;
+#endif
+}
+
+/* Merge the workers' CFL maxima into (*smax, *bad) in thread order, with the
+ * rule of sweep_line (a NaN, once seen, stays). */
+static int merge_lines(work_t *w, double *smax, int *bad)
+{
+    int e = ORC_OK;
+    for (int k = 0; k < w->nt; k++) {
+        const line_t *L = &w->line[k];
+        double a = L->smax;
+        if (isnan(a) || a > *smax) *smax = a;
+        if (L->bad) *bad = 1;
+        if (L->err) e = L->err;
+    }
+    return e;
+}
+
+static void clear_lines(work_t *w)
+{
+    for (int k = 0; k < w->nt; k++) { w->line[k].smax = 0.0; w->line[k].bad = 0; w->line[k].err = 0; }
 }
 
 /* One attempted step from w->a (interior holds Q^n) to w->d (Q^{n+1}) with
@@ -520,25 +600,35 @@ static int attempt(const orc_params *p, work_t *w, double t, double dt, double *
 {
     int nx = p->nx, ny = p->ny, e;
     *smax = 0.0; *bad = 0;
-    /* x1 sweep on Q^n */
+    /* x1 sweep on Q^n, one row per iteration */
     fill_ghosts_x(p, t, &w->a, 2);
+    clear_lines(w);
+#pragma omp parallel for schedule(static) num_threads(w->nt)
     for (int j = 0; j < ny; j++) {
+        line_t *L = &w->line[thread_id()];
         for (int k = 0; k < nx + 2 * GH; k++) {
             size_t s = idx(&w->a, k - GH, j);
-            w->lr[k] = w->a.R[s]; w->ln[k] = w->a.M[s]; w->lt[k] = w->a.N[s];
+            L->lr[k] = w->a.R[s]; L->ln[k] = w->a.M[s]; L->lt[k] = w->a.N[s];
         }
-        e = sweep_line(p->beta, dt, nx, w->lr, w->ln, w->lt, w->or_, w->on, w->ot, w->f, smax, bad);
-        if (e) return e;
+        double sm = 0.0;
+        int bd = 0;
+        int er = sweep_line(p->beta, dt, nx, L->lr, L->ln, L->lt, L->or_, L->on, L->ot, L->f, &sm, &bd);
+        if (er) L->err = er;
+        if (isnan(sm) || sm > L->smax) L->smax = sm;
+        if (bd) L->bad = 1;
         for (int i = 0; i < nx; i++) {
             size_t d = idx(&w->b, i, j);
-            w->b.R[d] = w->or_[i]; w->b.M[d] = w->on[i]; w->b.N[d] = w->ot[i];
+            w->b.R[d] = L->or_[i]; w->b.M[d] = L->on[i]; w->b.N[d] = L->ot[i];
         }
     }
+    e = merge_lines(w, smax, bad);
+    if (e) return e;
     /* Ghost rows of Q* on sides with analytic (Taylor) data: the x1 sweep
      * applied to the analytic Q^n of those rows (their own x ghosts by the
      * x side rules), so that the x2 sweep meets ghost values that went through
      * the same first fractional step as the interior.  Their interfaces do not
      * enter the CFL maximum. */
+    line_t *L0 = &w->line[0];
     for (int side = 2; side <= 3; side++) {
         if (p->bc[side] != BC_TAYLOR) continue;
         for (int l = 1; l <= 2; l++) {
@@ -550,40 +640,49 @@ static int attempt(const orc_params *p, work_t *w, double t, double dt, double *
             }
             for (int k = 0; k < nx + 2 * GH; k++) {
                 size_t s = idx(&w->a, k - GH, j);
-                w->lr[k] = w->a.R[s]; w->ln[k] = w->a.M[s]; w->lt[k] = w->a.N[s];
+                L0->lr[k] = w->a.R[s]; L0->ln[k] = w->a.M[s]; L0->lt[k] = w->a.N[s];
             }
             double ghost_smax = 0.0;
             int ghost_bad = 0;
-            e = sweep_line(p->beta, dt, nx, w->lr, w->ln, w->lt, w->or_, w->on, w->ot, w->f,
+            e = sweep_line(p->beta, dt, nx, L0->lr, L0->ln, L0->lt, L0->or_, L0->on, L0->ot, L0->f,
                            &ghost_smax, &ghost_bad);
             if (e) return e;
             for (int i = 0; i < nx; i++) {
                 size_t d = idx(&w->b, i, j);
-                w->b.R[d] = w->or_[i]; w->b.M[d] = w->on[i]; w->b.N[d] = w->ot[i];
+                w->b.R[d] = L0->or_[i]; w->b.M[d] = L0->on[i]; w->b.N[d] = L0->ot[i];
             }
         }
     }
-    if (p->geometry == GEOM_AXISYM) geometric_half_step(p, 0.5 * dt, &w->b);
-    /* x2 sweep on Q*: same scheme with components 2 and 3 swapped */
+    if (p->geometry == GEOM_AXISYM) geometric_half_step(p, 0.5 * dt, &w->b, w->nt);
+    /* x2 sweep on Q*: same scheme with components 2 and 3 swapped, one column
+     * per iteration */
     fill_ghosts_y_q1(p, t, &w->b, 2);
+    clear_lines(w);
+#pragma omp parallel for schedule(static) num_threads(w->nt)
     for (int i = 0; i < nx; i++) {
+        line_t *L = &w->line[thread_id()];
         for (int k = 0; k < ny + 2 * GH; k++) {
             size_t s = idx(&w->b, i, k - GH);
-            w->lr[k] = w->b.R[s]; w->ln[k] = w->b.N[s]; w->lt[k] = w->b.M[s];
+            L->lr[k] = w->b.R[s]; L->ln[k] = w->b.N[s]; L->lt[k] = w->b.M[s];
         }
-        e = sweep_line(p->beta, dt, ny, w->lr, w->ln, w->lt, w->or_, w->on, w->ot, w->f, smax, bad);
-        if (e) return e;
+        double sm = 0.0;
+        int bd = 0;
+        int er = sweep_line(p->beta, dt, ny, L->lr, L->ln, L->lt, L->or_, L->on, L->ot, L->f, &sm, &bd);
+        if (er) L->err = er;
+        if (isnan(sm) || sm > L->smax) L->smax = sm;
+        if (bd) L->bad = 1;
         for (int j = 0; j < ny; j++) {
             size_t d = idx(&w->c, i, j);
-            w->c.R[d] = w->or_[j]; w->c.N[d] = w->on[j]; w->c.M[d] = w->ot[j];
+            w->c.R[d] = L->or_[j]; w->c.N[d] = L->on[j]; w->c.M[d] = L->ot[j];
         }
     }
-    if (p->geometry == GEOM_AXISYM) geometric_half_step(p, 0.5 * dt, &w->c);
+    e = merge_lines(w, smax, bad);
+    if (e) return e;
+    if (p->geometry == GEOM_AXISYM) geometric_half_step(p, 0.5 * dt, &w->c, w->nt);
     /* source on Q** with one ghost layer */
     fill_ghosts_x(p, t, &w->c, 1);
     fill_ghosts_y(p, t, &w->c, 1);
-    source_step(p, dt, &w->c, &w->d);
-    return ORC_OK;
+    return source_step(p, dt, &w->c, &w->d, w->nt);
 }
 
 static int check_params(const orc_params *p)
@@ -685,6 +784,7 @@ int orc_run(const orc_params *p, double *R, double *M, double *N, long nsteps,
             continue;
         }
         retries = 0;
+#pragma omp parallel for schedule(static) num_threads(w.nt)
         for (int j = 0; j < p->ny; j++)
             for (int i = 0; i < p->nx; i++) {
                 size_t d = idx(&w.a, i, j);
