@@ -1,19 +1,20 @@
 """Benchmark: Mcell-updates/s of the fused finite-volume step on one MI355X.
 
-Workload (default): the FP32 Cartesian Gaussian-pulse case, 4096 x 4096
-cells, dx = 1e-4 m, water (c0 1500 m/s, rho0 1000 kg/m^3, beta 3.5,
-delta 4.3e-6 m^2/s), 2 MPa pulse with sigma = 20 cells at a seed-chosen
-centre plus 0.5% white noise (seed 2), zero-order-extrapolation sides, CFL
-0.9, 2000 steps.  A step is one accepted time step of the whole method
-(x1 sweep, x2 sweep, source, CFL control) over the grid.
+Workload (default): the Cartesian Gaussian-pulse case, 4096 x 4096 cells,
+dx = 1e-4 m, water (c0 1500 m/s, rho0 1000 kg/m^3, beta 3.5, delta
+4.3e-6 m^2/s), 2 MPa pulse with sigma = 20 cells at a seed-chosen centre
+plus 0.5% white noise (seed 2), zero-order-extrapolation sides, CFL 0.9.
+A step is one accepted time step of the whole method (x1 sweep, x2 sweep,
+source, CFL control) over the grid.
 
-Prints ONE JSON line.  Besides the headline FP32 figure it carries the FP64
-path on the same workload, the FP32 error against it, the batched form (64
-uneven simulations in one graph-replayed launch per step) against 64
-sequential launches, the throughput of the axisymmetric focused-source
-configs (8192 x 2048 FP32; 16384 x 8192 in FP32, FP16 and BF16 storage), the
-roofline of the step kernel and the FP64 CPU oracle timed on a bounded sample
-on the host.
+Prints ONE JSON line.  The headline is the FP64 path (the paper's
+arithmetic: all its simulations run in double precision).  Beside it: the
+FP32 path on the same workload with its error against FP64, the batched form
+(64 uneven simulations, one graph-replayed launch per step) against 64
+sequential launches, the axisymmetric focused-source configs (8192 x 2048
+FP32; 16384 x 8192 in FP32, FP16 and BF16 storage), the 3-D step, the
+roofline of the step kernels and the FP64 CPU oracle timed on a bounded
+sample on the host (one thread and every core of the process's CPU share).
 """
 import argparse
 import json
@@ -29,22 +30,31 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_CELL = {"f64": 48, "f32": 24, "f32_f16store": 12, "f32_bf16store": 12}
 
-# HBM bytes per launch of the FP32 step kernel on this workload, from two
-# rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE), each scaled by what the
-# same counter reads for a plain 1 GiB device copy (fetch x2.000, write x1.000);
-# profiles/k_step_f32_gaussian4096.md.  Valid only for the kernel sources and
-# build flags whose SHA-256 is recorded here: anything else reports null.
-PMC_TRAFFIC = {
-    "bytes_per_launch": 216.1e6 + 204.4e6,
-    "fetch_bytes": 216.1e6, "write_bytes": 204.4e6,
-    "valu_lane_ops_per_cell": 308.0,
-    "nx": 4096, "ny": 4096,
-    "sources": {
-        "fvna_device.hpp": "36224bdec71b2149af2a36c7e561432dc6c8d97c03d0f968f7e439323ef7115c",
-        "fvna_runtime.hip": "81331248debaae07efbe8311f94b596b7ab0a8c598f93549c7c276d4e917e5ec",
-        "build.py": "1709860880cb190303f24f18d1fde1d9184d0402975a6b07f4af871ebecdc2f1",
-    },
-}
+# Counter figures of the step kernels on this workload (4096 x 4096), from
+# rocprofv3 --pmc runs of this script: HBM bytes per launch from FETCH_SIZE,
+# then WRITE_SIZE, each scaled by what the same counter reads for a plain
+# 1 GiB device copy (fetch x2.000, write x1.000), and VALU lane-ops per
+# cell-update from SQ_INSTS_VALU x 64 / cells (profiles/k_step_*.md).  Each
+# entry is valid only for the kernel sources and build flags whose SHA-256 it
+# records: after any change they report null until profiled again.
+PMC = {}
+PMC_SOURCES = ("csrc/fvna_device.hpp", "csrc/fvna_runtime.hip", "build.py")
+
+
+def _sources_digest():
+    import hashlib
+    out = {}
+    for rel in PMC_SOURCES:
+        with open(os.path.join(ROOT, "paper_1311_3004_amd", rel), "rb") as f:
+            out[rel] = hashlib.sha256(f.read()).hexdigest()
+    return out
+
+
+def pmc_entry(kernel, nx, ny):
+    e = PMC.get(kernel)
+    if e is None or (nx, ny) != (e["nx"], e["ny"]) or e["sources"] != _sources_digest():
+        return None
+    return e
 
 
 # Vector-ALU rate of the chip counted as the profile counts SQ_INSTS_VALU:
@@ -52,31 +62,23 @@ PMC_TRAFFIC = {
 VALU_PEAK_LANE_OPS = 256 * 64 * 2.4e9
 
 
-def measured_valu(nx, ny, kernel_s):
-    """VALU lane-ops per cell-update of the profiled kernel (SQ_INSTS_VALU x 64
-    / cells) and the rate they run at in the live launch, against the chip's
-    non-packed vector rate; None if the kernel sources or grid differ from the
-    profiled ones."""
-    if measured_traffic(nx, ny) is None:
+def measured_valu(kernel, nx, ny, kernel_s):
+    """VALU lane-ops per cell-update of the profiled kernel and the rate they
+    run at in the live launch, against the chip's non-packed vector rate; None
+    if the kernel sources or grid differ from the profiled ones."""
+    e = pmc_entry(kernel, nx, ny)
+    if e is None:
         return None
-    ops = PMC_TRAFFIC["valu_lane_ops_per_cell"]
+    ops = e["valu_lane_ops_per_cell"]
     rate = ops * nx * ny / kernel_s
     return {"lane_ops_per_cell": ops, "achieved": round(rate / 1e12, 2), "peak": round(VALU_PEAK_LANE_OPS / 1e12, 2),
             "unit": "T lane-ops/s", "frac": round(rate / VALU_PEAK_LANE_OPS, 4)}
 
 
-def measured_traffic(nx, ny):
-    """PMC bytes per launch if the kernel sources and grid are the profiled ones."""
-    import hashlib
-    if (nx, ny) != (PMC_TRAFFIC["nx"], PMC_TRAFFIC["ny"]):
-        return None
-    for name, digest in PMC_TRAFFIC["sources"].items():
-        sub = () if name == "build.py" else ("csrc",)
-        path = os.path.join(ROOT, "paper_1311_3004_amd", *sub, name)
-        with open(path, "rb") as f:
-            if hashlib.sha256(f.read()).hexdigest() != digest:
-                return None
-    return PMC_TRAFFIC["bytes_per_launch"]
+def measured_traffic(kernel, nx, ny):
+    """PMC HBM bytes per launch if the kernel sources and grid are the profiled ones."""
+    e = pmc_entry(kernel, nx, ny)
+    return None if e is None else e["fetch_bytes"] + e["write_bytes"]
 
 
 def log(*a):
@@ -177,19 +179,117 @@ def three_d(n=256, steps=20):
             "bytes_per_cell_update": 32}
 
 
-def cpu_baseline(w, steps):
-    """FP64 oracle on the host: `steps` steps of the same workload, full grid."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_threads():
+    """Threads the oracle may use: the process's CPU share (OMP_NUM_THREADS
+    when set, else the CPUs this process may run on)."""
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        return int(env)
+    return len(os.sched_getaffinity(0))
+
+
+def cpu_baseline(w, steps, threads):
+    """FP64 oracle on the host: `steps` steps of the same workload, full grid,
+    on `threads` threads (OpenMP over rows; bitwise identical results)."""
     import oracle
     med = w["medium"]
     p = oracle.make_params_si(w["nx"], w["ny"], w["dx"], med["c0"], med["rho0"], med["beta"],
                               med["delta"], bc=w["bc"])
     rp, mx, my = w["state"]
     R, M, N = rp / med["rho0"], mx / (med["rho0"] * med["c0"]), my / (med["rho0"] * med["c0"])
-    t0 = time.perf_counter()
-    _, _, _, info = oracle.run(p, R, M, N, steps)
-    dt = time.perf_counter() - t0
+    oracle.set_threads(threads)
+    try:
+        t0 = time.perf_counter()
+        _, _, _, info = oracle.run(p, R, M, N, steps)
+        dt = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(1)
     assert info["status"] == 0
     return w["nx"] * w["ny"] * steps / dt / 1e6, dt
+
+
+def step_leg(fvna, w, precision, steps, warmup, tile_rows=0):
+    """One precision on the main workload: throughput, live kernel time, state."""
+    cells = w["nx"] * w["ny"]
+    s = fvna.sim_from_workload(w, precision=precision, tile_rows=tile_rows)
+    r = timed_run(s, steps, warmup)
+    v = cells * r["accepted"] / r["event_s"] / 1e6
+    ms_k, gbs = kernel_roofline(s, precision, cells)
+    R = s.fvna_get_state()[0]
+    tr = s.fvna_get_tile_rows()
+    s.fvna_destroy()
+    kernel = {"f64": "k_step<double,double,0>", "f32": "k_step<float,float,0>"}[precision]
+    log(f"[bench] {precision}: {v:.1f} Mcell/s, {r['event_s'] * 1e3 / steps:.3f} ms/step, "
+        f"step kernel {ms_k:.4f} ms = {gbs:.0f} GB/s algorithmic")
+    return {"value": v, "run": r, "kernel_ms": ms_k, "gbs": gbs, "R": R, "tile_rows": tr, "kernel": kernel}
+
+
+def roofline_of(leg, precision, nx, ny):
+    cells = nx * ny
+    k = leg["kernel"]
+    return {"bound": "hbm", "achieved": round(leg["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(leg["gbs"] / HBM_PEAK_GBS, 4), "traffic": measured_traffic(k, nx, ny),
+            "kernel": k, "kernel_ms": round(leg["kernel_ms"], 4),
+            "bytes_per_launch": BYTES_PER_CELL[precision] * cells,
+            "valu": measured_valu(k, nx, ny, leg["kernel_ms"] * 1e-3)}
+
+
+def batched_leg(fvna, inputs, nb):
+    """64 uneven simulations in one batch against 64 sequential contexts:
+    throughput of each and bitwise equality of every member's final state."""
+    import torch
+    sims = inputs.c4_batch()
+    plist = [fvna.make_params(x["nx"], x["ny"], x["dx"], x["medium"], bc=x["bc"], precision="f32")
+             for x in sims]
+    B = fvna.Batch(plist)
+    for k, x in enumerate(sims):
+        B.fvna_batch_set_state(k, *x["state"])
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(B.stream)
+    B.fvna_batch_step(nb)
+    B.fvna_batch_sync()
+    e1.record(B.stream)
+    torch.cuda.synchronize()
+    tb = e0.elapsed_time(e1) / 1e3
+    bcells = sum(x["nx"] * x["ny"] for x in sims)
+    vb = bcells * nb / tb / 1e6
+    msb = B.fvna_batch_time_step_kernel(5)
+    gbsb = 24 * bcells / (msb * 1e-3) / 1e9
+    tseq = 0.0
+    same = 0
+    for k, x in enumerate(sims):
+        s = fvna.Sim(plist[k])
+        s.fvna_set_state(*x["state"])
+        torch.cuda.synchronize()
+        a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a0.record(s.stream)
+        s.fvna_step(nb)
+        s.fvna_sync()
+        a1.record(s.stream)
+        torch.cuda.synchronize()
+        tseq += a0.elapsed_time(a1) / 1e3
+        same += all(np.array_equal(u, v) for u, v in zip(s.fvna_get_state(), B.fvna_batch_get_state(k)))
+        s.fvna_destroy()
+    vseq = bcells * nb / tseq / 1e6
+    log(f"[bench] batched: {vb:.1f} Mcell/s (kernel {gbsb:.0f} GB/s) vs sequential {vseq:.1f}; "
+        f"bitwise equal {same}/{len(sims)}")
+    B.fvna_batch_destroy()
+    return {"value": round(vb, 1), "unit": "Mcell-updates/s", "sims": len(sims), "cells": bcells, "steps": nb,
+            "sequential_value": round(vseq, 1), "speedup_vs_sequential": round(vb / vseq, 3),
+            "kernel_ms": round(msb, 4), "hbm_frac": round(gbsb / HBM_PEAK_GBS, 4),
+            "bitwise_equal_members": same}
 
 
 def main():
@@ -199,14 +299,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--nx", type=int, default=4096)
     ap.add_argument("--ny", type=int, default=4096)
-    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 leg of the main workload")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-other", action="store_true", help="skip the axisymmetric configs")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3-D leg")
+    ap.add_argument("--fp32-only", action="store_true",
+                    help="run only the FP32 leg of the main workload (for its profiles)")
     ap.add_argument("--other-steps", type=int, default=200)
-    ap.add_argument("--autotune", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-steps", type=int, default=2, help="oracle steps on one thread")
+    ap.add_argument("--cpu-steps-all", type=int, default=8, help="oracle steps on every core of the share")
     ap.add_argument("--batch-steps", type=int, default=1000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
@@ -222,130 +324,74 @@ def main():
 
     torch.cuda.set_device(0)
     w = inputs.c2_pulse_fp32(args.nx, args.ny)
-    cells = w["nx"] * w["ny"]
-    med = w["medium"]
-    log(f"[bench] workload {w['name']}, {args.steps} steps (+{args.warmup} warm-up)")
-
-    # ---- headline: FP32 ----
-    s32 = fvna.sim_from_workload(w, precision="f32")
-    if args.autotune:
-        log(f"[bench] autotuned tile_rows = {s32.fvna_autotune()}")
-        s32.fvna_set_state(*w["state"])
-    r32 = timed_run(s32, args.steps, args.warmup)
-    v32 = cells * r32["accepted"] / r32["event_s"] / 1e6
-    ms_k, gbs = kernel_roofline(s32, "f32", cells)
-    log(f"[bench] fp32: {v32:.1f} Mcell/s, {r32['event_s'] * 1e3 / args.steps:.3f} ms/step, "
-        f"step kernel {ms_k:.3f} ms = {gbs:.0f} GB/s algorithmic")
-    R32 = s32.fvna_get_state()[0]
-    tile_rows = s32.fvna_get_tile_rows()
-    s32.fvna_destroy()
+    nx, ny = w["nx"], w["ny"]
+    workload = f"gaussian-pulse {nx}x{ny}"
+    log(f"[bench] workload {workload}, {args.steps} steps (+{args.warmup} warm-up)")
 
     extra = {}
-    # ---- FP64 path, same workload, and the FP32 error against it ----
-    if not args.no_fp64:
-        s64 = fvna.sim_from_workload(w, precision="f64", tile_rows=tile_rows)
-        r64 = timed_run(s64, args.steps, args.warmup)
-        v64 = cells * r64["accepted"] / r64["event_s"] / 1e6
-        ms64, gbs64 = kernel_roofline(s64, "f64", cells)
-        R64 = s64.fvna_get_state()[0]
-        s64.fvna_destroy()
-        err = float(np.max(np.abs(R32 - R64)) / np.max(np.abs(R64)))
-        l2 = float(np.sqrt(np.mean((R32 - R64) ** 2)) / np.sqrt(np.mean(R64 ** 2)))
-        log(f"[bench] fp64: {v64:.1f} Mcell/s, kernel {ms64:.3f} ms = {gbs64:.0f} GB/s; "
-            f"fp32 max|dp|/p_peak = {err:.2e}")
-        extra["fp64"] = {"value": round(v64, 1), "unit": "Mcell-updates/s",
-                         "ms_per_step": round(r64["event_s"] * 1e3 / args.steps, 4),
-                         "kernel_ms": round(ms64, 4), "hbm_frac": round(gbs64 / HBM_PEAK_GBS, 4)}
-        extra["fp32_error_vs_fp64"] = {"max_abs_dp_over_p_peak": err, "rel_l2": l2,
-                                       "steps": args.warmup + args.steps,
-                                       "time_rel_diff": abs(r32["t"] - r64["t"]) / r64["t"]}
-        extra["fp32_over_fp64"] = round(v32 / v64, 3)
+    if args.fp32_only:
+        l32 = step_leg(fvna, w, "f32", args.steps, args.warmup)
+        head, head_prec = l32, "f32"
+    else:
+        # ---- headline: FP64, the paper's arithmetic ----
+        l64 = step_leg(fvna, w, "f64", args.steps, args.warmup)
+        head, head_prec = l64, "f64"
+        # ---- FP32 on the same workload, and its error against FP64 ----
+        if not args.no_fp32:
+            l32 = step_leg(fvna, w, "f32", args.steps, args.warmup)
+            R32, R64 = l32["R"], l64["R"]
+            err = float(np.max(np.abs(R32 - R64)) / np.max(np.abs(R64)))
+            l2 = float(np.sqrt(np.mean((R32 - R64) ** 2)) / np.sqrt(np.mean(R64 ** 2)))
+            log(f"[bench] fp32 max|dp|/p_peak vs fp64 = {err:.2e}")
+            extra["fp32"] = {"value": round(l32["value"], 1), "unit": "Mcell-updates/s",
+                             "ms_per_step": round(l32["run"]["event_s"] * 1e3 / args.steps, 4),
+                             "tile_rows": l32["tile_rows"], "roofline": roofline_of(l32, "f32", nx, ny),
+                             "error_vs_fp64": {"max_abs_dp_over_p_peak": err, "rel_l2": l2,
+                                               "steps": args.warmup + args.steps,
+                                               "time_rel_diff": abs(l32["run"]["t"] - l64["run"]["t"]) /
+                                               l64["run"]["t"]},
+                             "over_fp64": round(l32["value"] / l64["value"], 3)}
+    r = head["run"]
 
-    # ---- batched form: 64 uneven simulations vs 64 sequential runs ----
-    if not args.no_batch:
-        sims = inputs.c4_batch()
-        plist = [fvna.make_params(x["nx"], x["ny"], x["dx"], x["medium"], bc=x["bc"], precision="f32")
-                 for x in sims]
-        B = fvna.Batch(plist)
-        for k, x in enumerate(sims):
-            B.fvna_batch_set_state(k, *x["state"])
-        nb = args.batch_steps
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(B.stream)
-        B.fvna_batch_step(nb)
-        B.fvna_batch_sync()
-        e1.record(B.stream)
-        torch.cuda.synchronize()
-        tb = e0.elapsed_time(e1) / 1e3
-        bcells = sum(x["nx"] * x["ny"] for x in sims)
-        vb = bcells * nb / tb / 1e6
-        msb = B.fvna_batch_time_step_kernel(5)
-        gbsb = 24 * bcells / (msb * 1e-3) / 1e9
-        # sequential reference: same simulations, one context each, run one after another
-        tseq = 0.0
-        same = True
-        for k, x in enumerate(sims):
-            s = fvna.Sim(plist[k])
-            s.fvna_set_state(*x["state"])
-            torch.cuda.synchronize()
-            a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a0.record(s.stream)
-            s.fvna_step(nb)
-            s.fvna_sync()
-            a1.record(s.stream)
-            torch.cuda.synchronize()
-            tseq += a0.elapsed_time(a1) / 1e3
-            if k % 8 == 0:
-                same &= all(np.array_equal(u, v) for u, v in zip(s.fvna_get_state(), B.fvna_batch_get_state(k)))
-            s.fvna_destroy()
-        vseq = bcells * nb / tseq / 1e6
-        log(f"[bench] batched: {vb:.1f} Mcell/s (kernel {gbsb:.0f} GB/s) vs sequential {vseq:.1f}; "
-            f"bitwise equal (sampled) {same}")
-        extra["batched"] = {"value": round(vb, 1), "unit": "Mcell-updates/s", "sims": len(sims),
-                            "cells": bcells, "steps": nb, "sequential_value": round(vseq, 1),
-                            "speedup_vs_sequential": round(vb / vseq, 3),
-                            "hbm_frac": round(gbsb / HBM_PEAK_GBS, 4),
-                            "bitwise_equal_sampled": bool(same)}
-        B.fvna_batch_destroy()
-
-    if not args.no_other:
+    if not args.fp32_only and not args.no_batch:
+        extra["batched"] = batched_leg(fvna, inputs, args.batch_steps)
+    if not args.fp32_only and not args.no_other:
         extra["other_configs"] = other_configs(fvna, inputs, args.other_steps)
-    if not args.no_3d:
+    if not args.fp32_only and not args.no_3d:
         extra["three_d"] = three_d()
 
     out = {
         "metric": "Mcell-updates/s and % HBM roofline, FP32/batched vs FP64 at stated error",
-        "value": round(v32, 1),
+        "value": round(head["value"], 1),
         "unit": "Mcell-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(r32["event_s"] * 1e3 / args.steps, 4),
+        "ms_per_step": round(r["event_s"] * 1e3 / args.steps, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": head_prec,
         "data": "synthetic",
-        "config": {"workload": w["name"], "nx": w["nx"], "ny": w["ny"], "dx_m": w["dx"],
+        "config": {"workload": workload, "precision": head_prec, "nx": nx, "ny": ny, "dx_m": w["dx"],
                    "steps": args.steps, "boundaries": "zero-order extrapolation", "seed": 2,
-                   "cfl_target": 0.9, "tile_rows": tile_rows},
-        "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(w["nx"], w["ny"]),
-                     "kernel": "k_step<float,float,0>", "kernel_ms": round(ms_k, 4),
-                     "bytes_per_launch": BYTES_PER_CELL["f32"] * cells,
-                     "valu": measured_valu(w["nx"], w["ny"], ms_k * 1e-3)},
-        "wall_s": round(r32["wall_s"], 4),
-        "nu_mean": r32["nu_mean"], "nu_std": r32["nu_std"], "rejected": r32["rejected"],
+                   "cfl_target": 0.9, "tile_rows": head["tile_rows"]},
+        "roofline": roofline_of(head, head_prec, nx, ny),
+        "wall_s": round(r["wall_s"], 4),
+        "nu_mean": r["nu_mean"], "nu_std": r["nu_std"], "rejected": r["rejected"],
     }
     out.update(extra)
-    if not args.no_cpu:
-        v_cpu, t_cpu = cpu_baseline(w, args.cpu_steps)
-        log(f"[bench] oracle on host: {v_cpu:.2f} Mcell/s ({t_cpu:.1f} s)")
-        out["cpu_baseline"] = {"value": round(v_cpu, 3), "unit": "Mcell-updates/s", "cores": 1,
-                               "kind": "oracle",
-                               "sample": f"{args.cpu_steps} steps of the same workload on the full "
-                                         f"{w['nx']}x{w['ny']} grid, FP64, 1 thread"}
+    if not args.no_cpu and not args.fp32_only:
+        nt = cpu_threads()
+        v1, t1 = cpu_baseline(w, args.cpu_steps, 1)
+        vn, tn = cpu_baseline(w, args.cpu_steps_all, nt)
+        log(f"[bench] oracle on host: {v1:.2f} Mcell/s on 1 thread ({t1:.1f} s), "
+            f"{vn:.2f} Mcell/s on {nt} threads ({tn:.1f} s)")
+        out["cpu_baseline"] = {"value": round(vn, 3), "unit": "Mcell-updates/s", "cores": nt, "kind": "oracle",
+                               "sample": f"{args.cpu_steps_all} steps of the same workload on the full "
+                                         f"{nx}x{ny} grid, FP64, {nt} threads (OpenMP over rows)",
+                               "single_thread": {"value": round(v1, 3), "steps": args.cpu_steps},
+                               "nproc": os.cpu_count(), "cpu_model": cpu_model()}
     if args.copy_calibration:
         a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda:0").fill_(1)
         b = torch.empty_like(a)

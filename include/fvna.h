@@ -166,7 +166,8 @@ fvna_status fvna_create(const fvna_params* p, void* state_a, void* state_b, void
 
 /* Change the boundary kind of one side (0 x-, 1 x+, 2 y-, 3 y+).  Periodic
  * must be set on both sides of an axis; SOURCE only on side 0; the
- * axisymmetric geometry needs REFLECT on side 2. */
+ * axisymmetric geometry needs REFLECT on side 2.  Waits for the context's
+ * stream first when steps were enqueued (the captured step graph is rebuilt). */
 fvna_status fvna_set_bc(fvna_ctx* c, int32_t side, int32_t bc);
 
 /* Parameters of the focused source (side must be 0).  Fills the per-row
@@ -177,7 +178,8 @@ fvna_status fvna_set_source(fvna_ctx* c, int32_t side, const fvna_source* s);
 
 /* Parameters of the Taylor profile used by TAYLOR sides (eq. OurTaylorS with
  * the rotation of Sec. 4.1): p' = -A tanh((xi - c0 t)/w), xi = (x - x0) cos(angle)
- * + y sin(angle), rho u = (p'/c0) (cos, sin), w = delta rho0 c0 / (beta A). */
+ * + y sin(angle), rho u = (p'/c0) (cos, sin), w = delta rho0 c0 / (beta A).
+ * Waits for the context's stream first when steps were enqueued. */
 fvna_status fvna_set_taylor(fvna_ctx* c, double amplitude_pa, double x0_m, double angle);
 
 /* Copy a host state in: rho' [kg/m^3], rho u, rho v [kg m^-2 s^-1], each [ny][nx]
@@ -213,8 +215,10 @@ fvna_status fvna_shift(fvna_ctx* c, int32_t ncols);
  * state is checked after every check_every-th accepted step (counted across
  * calls by `phase`), and once t >= t1 the origin moves to
  * quantum * floor((t - t1) c0 / (dx quantum)) cells from the start (fvna_shift
- * by the difference, at most nx).  The source's second stage (fvna_source
- * .stage2_time, normally t1) is set separately. */
+ * by the difference; a move of nx cells or more leaves undisturbed medium in
+ * the whole domain, and the path offset the recorder uses still advances by
+ * the whole move).  The source's second stage (fvna_source .stage2_time,
+ * normally t1) is set separately. */
 typedef struct {
     double t1;                 /* [s], finite */
     int32_t check_every;       /* >= 1 */
@@ -246,7 +250,8 @@ fvna_status fvna_step_window(fvna_ctx* c, const fvna_window* w, fvna_window_stat
  * was (the kernel is idempotent).  The arrays are caller-owned device memory
  * and must outlive the recording; the caller initialises row_max (e.g. to
  * -inf) and the probe arrays.  fvna_set_recorder synchronises the stream;
- * NULL stops recording.  FVNA_E_INVALID for a row outside the grid, missing
+ * NULL stops recording.  fvna_set_state and fvna_set_clock restart the step
+ * count, and with it the probe index: the next accepted step is k = 1 again.  FVNA_E_INVALID for a row outside the grid, missing
  * arrays, path_len < 1 or probe_col < -1 (-1: no probe). */
 typedef struct {
     int32_t row;

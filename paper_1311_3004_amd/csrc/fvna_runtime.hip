@@ -262,6 +262,37 @@ __global__ void k_dt0(SimDesc d)
     c->dt = d.cfl_target / smax;
 }
 
+// Per-row table of the focused source (eq. hifuBC), rows r = j + 1/2: the
+// focusing delay f r^2/(2F) reduced modulo one period, the direction cosines
+// F/h and -r/h with h = sqrt(r^2 + F^2), and the whole delay.  FP64 with
+// correctly rounded division and square root.
+__global__ void k_src_table(double* __restrict__ tab, int ny, double f, double F)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= ny) return;
+    const double r = j + 0.5;
+    const double delay = f * (r * r / (2.0 * F));
+    const double h = sqrt(r * r + F * F);
+    tab[4 * (size_t)j] = delay - floor(delay);
+    tab[4 * (size_t)j + 1] = F / h;
+    tab[4 * (size_t)j + 2] = -r / h;
+    tab[4 * (size_t)j + 3] = delay;
+}
+
+// Whole clock of one simulation written from its arguments (every field the
+// controller and the step kernel read starts defined, counters at zero).
+__global__ void k_clock_init(Clock* __restrict__ c, double t, double dt, int cur, long long target)
+{
+    if (threadIdx.x != 0) return;
+    Clock h;
+    __builtin_memset(&h, 0, sizeof(h));
+    h.t = t;
+    h.dt = dt;
+    h.cur = cur;
+    h.target = target;
+    *c = h;
+}
+
 // Host doubles (SI, staged on the device) -> stored dimensionless field.
 template <typename S, typename T>
 __global__ void k_import(SimDesc d, const double* __restrict__ src, int field, int row0, int nrows,
@@ -651,8 +682,12 @@ static void launch_attempt(fvna_ctx* c, hipStream_t s)
     if (c->recording) c->L.record(c->d, c->rec, s);
 }
 
+// Destroy the captured graph after every launch of it already enqueued on the
+// context's stream has finished (a graph replay may still be in flight when a
+// setter changes what the next capture must hold).
 static void drop_graph(fvna_ctx* c)
 {
+    if (c->exec || c->graph) (void)hipStreamSynchronize(c->stream);
     if (c->exec) (void)hipGraphExecDestroy(c->exec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
     c->exec = nullptr;
@@ -702,6 +737,12 @@ static fvna_status reset_clock(fvna_ctx* c, double t_dimless, double dt_dimless,
     h.x_off = x_off;
     HIP_TRY(hipStreamSynchronize(c->stream));
     HIP_TRY(hipMemcpy(c->clk, &h, sizeof(Clock), hipMemcpyHostToDevice));
+    if (c->recording) {
+        // the step count restarts at 0: the recorder counts from here on
+        // (its descriptor is a kernel argument of the captured graph)
+        c->rec.base = 0;
+        drop_graph(c);
+    }
     if (!(dt_dimless > 0.0)) {
         c->L.dry(c->d, c->stream);
         HIP_TRY(hipGetLastError());
@@ -785,10 +826,11 @@ fvna_status fvna_set_bc(fvna_ctx* c, int32_t side, int32_t bc)
     return FVNA_OK;
 }
 
-fvna_status fvna_set_source(fvna_ctx* c, int32_t side, const fvna_source* s)
+// Check a focused-source description and put it into a simulation
+// descriptor (dimensionless); the per-row table goes to `tab` on `stream`.
+static fvna_status apply_source(SimDesc& d, const fvna_params& p, const fvna_source* s, double* tab,
+                                hipStream_t stream)
 {
-    if (!c || !s) return fail(FVNA_E_INVALID, "NULL argument");
-    if (side != 0) return fail(FVNA_E_INVALID, "the focused source is only available on side x-");
     if (!(s->freq > 0) || !(s->focal_length > 0) || !(s->aperture >= 0))
         return fail(FVNA_E_INVALID, "need freq > 0, focal_length > 0, aperture >= 0");
     if (s->envelope == FVNA_ENV_RAMP) {
@@ -800,33 +842,31 @@ fvna_status fvna_set_source(fvna_ctx* c, int32_t side, const fvna_source* s)
     }
     if (s->second_stage != 0 && (s->second_stage != 1 || !std::isfinite(s->stage2_time)))
         return fail(FVNA_E_INVALID, "second_stage must be 0 or 1, with a finite stage2_time");
-    const fvna_params& p = c->p;
-    c->d.sr_amp = s->p_surface / (p.rho0 * p.c0 * p.c0);
-    c->d.sr_freq = s->freq * p.dx / p.c0;
-    c->d.sr_F = s->focal_length / p.dx;
-    c->d.sr_ap = s->aperture / p.dx;
-    c->d.sr_ramp = s->envelope == FVNA_ENV_RAMP ? s->ramp_cycles : 1.0;
-    c->d.sr_env = s->envelope;
-    c->d.sr_W = s->envelope == FVNA_ENV_PACKET ? s->packet_cycles : 1.0;
-    c->d.sr_t2 = s->second_stage ? s->stage2_time * p.c0 / p.dx : INFINITY;
-    // per-row table: focusing delay reduced modulo one period, direction
-    // cosines, and the whole delay (for the packet envelope)
-    std::vector<double> tab(4 * (size_t)p.ny);
-    const double f = c->d.sr_freq, F = c->d.sr_F;
-    for (int j = 0; j < p.ny; ++j) {
-        const double r = j + 0.5;
-        const double delay = f * (r * r / (2.0 * F));
-        const double h = std::sqrt(r * r + F * F);
-        tab[4 * (size_t)j] = delay - std::floor(delay);
-        tab[4 * (size_t)j + 1] = F / h;
-        tab[4 * (size_t)j + 2] = -r / h;
-        tab[4 * (size_t)j + 3] = delay;
-    }
-    double* dtab = (double*)(c->scratch + OFF_SRCTAB);
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    HIP_TRY(hipMemcpy(dtab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice));
-    c->d.src_tab = dtab;
+    d.sr_amp = s->p_surface / (p.rho0 * p.c0 * p.c0);
+    d.sr_freq = s->freq * p.dx / p.c0;
+    d.sr_F = s->focal_length / p.dx;
+    d.sr_ap = s->aperture / p.dx;
+    d.sr_ramp = s->envelope == FVNA_ENV_RAMP ? s->ramp_cycles : 1.0;
+    d.sr_env = s->envelope;
+    d.sr_W = s->envelope == FVNA_ENV_PACKET ? s->packet_cycles : 1.0;
+    d.sr_t2 = s->second_stage ? s->stage2_time * p.c0 / p.dx : INFINITY;
+    hipLaunchKernelGGL(k_src_table, dim3((p.ny + 255) / 256), dim3(256), 0, stream, tab, p.ny, d.sr_freq, d.sr_F);
+    HIP_TRY(hipGetLastError());
+    d.src_tab = tab;
+    return FVNA_OK;
+}
+
+fvna_status fvna_set_source(fvna_ctx* c, int32_t side, const fvna_source* s)
+{
+    if (!c || !s) return fail(FVNA_E_INVALID, "NULL argument");
+    if (side != 0) return fail(FVNA_E_INVALID, "the focused source is only available on side x-");
     drop_graph(c);
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    SimDesc d = c->d;
+    fvna_status st = apply_source(d, c->p, s, (double*)(c->scratch + OFF_SRCTAB), c->stream);
+    if (st) return st;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->d = d;
     return FVNA_OK;
 }
 
@@ -996,7 +1036,12 @@ fvna_status fvna_step_window(fvna_ctx* c, const fvna_window* w, fvna_window_stat
         if (!(h.t >= t1)) continue;
         const int64_t target = (int64_t)w->quantum * (int64_t)std::floor((h.t - t1) / w->quantum);
         if (target <= st->x_off) continue;
-        const int64_t move = std::min<int64_t>(target - st->x_off, p.nx);
+        // a move of nx or more columns leaves undisturbed medium everywhere;
+        // the device offset still advances by the whole move, so that path
+        // columns (recorder) and st->x_off stay equal
+        const int64_t move = target - st->x_off;
+        if (move > (int64_t)INT32_MAX - (int64_t)p.nx)
+            return fail(FVNA_E_INVALID, "moving-domain jump too large");
         c->L.shift(c->d, (int)move, c->stream);
         HIP_TRY(hipGetLastError());
         st->x_off = target;
@@ -1030,6 +1075,20 @@ static fvna_status export_window(fvna_ctx* c, int i0, int j0, int ni, int nj, do
 static fvna_status export_state(fvna_ctx* c, double* rho_p, double* mom_x, double* mom_y)
 {
     return export_window(c, 0, 0, c->p.nx, c->p.ny, rho_p, mom_x, mom_y);
+}
+
+static void stats_from_clock(const Clock& h, const fvna_params& p, fvna_stats* st)
+{
+    const double tu = p.dx / p.c0;
+    st->t = h.t * tu;
+    st->dt_next = h.dt * tu;
+    st->nu_last = h.nu_last;
+    st->nu_mean = h.nu_mean;
+    st->nu_std = h.nu_count > 0 ? std::sqrt(h.nu_m2 / (double)h.nu_count) : 0.0;
+    st->steps = h.accepted;
+    st->rejected = h.rejected;
+    st->status = h.status;
+    st->status_step = h.status_step;
 }
 
 static fvna_status stats_of(fvna_ctx* c, fvna_stats* st)
@@ -1436,3 +1495,4 @@ void fvna_batch_destroy(fvna_batch* b)
 }
 
 }  // extern "C"
+

@@ -388,6 +388,14 @@ class Batch:
             pass
 
 
+def make_source(freq, p_surface, focal_length, aperture, ramp_cycles=3.0, envelope="ramp",
+                packet_cycles=4.0, stage2_time=None):
+    env = ENVELOPES[envelope] if isinstance(envelope, str) else int(envelope)
+    return fvna_source(float(freq), float(p_surface), float(focal_length), float(aperture),
+                       float(ramp_cycles), env, float(packet_cycles), int(stage2_time is not None),
+                       float(stage2_time) if stage2_time is not None else 0.0)
+
+
 def sim_from_workload(w, device="cuda:0", precision=None, **over):
     """Create a Sim for a workload dict of paper_1311_3004_amd.inputs and load its state."""
     kw = dict(bc=w["bc"], geometry=w["geometry"], precision=precision or w["precision"],

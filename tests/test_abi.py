@@ -131,3 +131,4 @@ def test_3d_library_exports_every_declared_symbol_and_matches_its_struct():
     assert int(got["size"]) == ctypes.sizeof(f3.fvna3_params)
     for field, _ in f3.fvna3_params._fields_:
         assert int(got[field]) == getattr(f3.fvna3_params, field).offset, field
+
