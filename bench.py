@@ -37,8 +37,20 @@ BYTES_PER_CELL = {"f64": 48, "f32": 24, "f32_f16store": 12, "f32_bf16store": 12}
 # cell-update from SQ_INSTS_VALU x 64 / cells (profiles/k_step_*.md).  Each
 # entry is valid only for the kernel sources and build flags whose SHA-256 it
 # records: after any change they report null until profiled again.
-PMC = {}
-PMC_SOURCES = ("csrc/fvna_device.hpp", "csrc/fvna_runtime.hip", "build.py")
+PMC_SOURCES = ("csrc/fvna_device.hpp", "csrc/fvna_step.hpp", "build.py")
+_PROFILED = {
+    "csrc/fvna_device.hpp": "36224bdec71b2149af2a36c7e561432dc6c8d97c03d0f968f7e439323ef7115c",
+    "csrc/fvna_step.hpp": "bdaa87da40e74c672a969a9b5e399e58b6871975b76743ca535f1ce64673c707",
+    "build.py": "02eda4061ab4ab18fbd0c2e868524ec4e9acf39f5fa26d0513e48c2fca74259e",
+}
+PMC = {
+    # profiles/k_step_f64_gaussian4096.md
+    "k_step<double,double,0>": {"nx": 4096, "ny": 4096, "fetch_bytes": 4.2294e+08, "write_bytes": 4.0520e+08,
+                                "valu_lane_ops_per_cell": 484.6, "sources": _PROFILED},
+    # profiles/k_step_f32_gaussian4096.md
+    "k_step<float,float,0>": {"nx": 4096, "ny": 4096, "fetch_bytes": 2.1615e+08, "write_bytes": 2.0438e+08,
+                              "valu_lane_ops_per_cell": 307.9, "sources": _PROFILED},
+}
 
 
 def _sources_digest():

@@ -5,7 +5,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc", "fvna_runtime.hip")
-DEPS = [SRC, os.path.join(HERE, "csrc", "fvna_device.hpp"),
+DEPS = [SRC, os.path.join(HERE, "csrc", "fvna_device.hpp"), os.path.join(HERE, "csrc", "fvna_step.hpp"),
         os.path.join(os.path.dirname(HERE), "include", "fvna.h")]
 LIB = os.path.join(HERE, "libfvna.so")
 

@@ -23,6 +23,7 @@
 
 #include "../../include/fvna.h"
 #include "fvna_device.hpp"
+#include "fvna_step.hpp"
 
 using namespace fvna;
 
@@ -82,60 +83,6 @@ __global__ void k_ctrl_batch(const SimDesc* __restrict__ descs, int n)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k < n) control(descs[k]);
-}
-
-// Waves per SIMD the register allocation must allow: three for FP32 compute
-// (168 VGPRs, no spills; with tiles that fill every slot in one round this
-// measured 9% faster than four waves at 128 VGPRs on a 4096^2 grid and level
-// on 8192^2), two for FP64.
-#ifndef FVNA_F32_WAVES_PER_SIMD
-#define FVNA_F32_WAVES_PER_SIMD 3
-#endif
-template <typename T> struct Occupancy { static constexpr int waves = sizeof(T) == 8 ? 2 : FVNA_F32_WAVES_PER_SIMD; };
-
-// One attempted step over the whole grid.  force = 1 (timing): run even when
-// no step is owed.
-// Workgroups are handed to the XCDs round-robin (block b to XCD b mod 8,
-// each with its own L2).  Block b is given logical block start(x) + b / 8 of
-// XCD x = b mod 8, so every XCD works on one contiguous run of tiles, which
-// in row-major tile order is a band of whole segment rows: the halo columns
-// of side-by-side strips and the warm-up rows of stacked segments are then
-// read into the same L2.  A bijection of block indices; results do not
-// depend on it.
-constexpr int XCDS = 8;
-__device__ __forceinline__ int xcd_block(int b, int nblocks)
-{
-    const int x = b % XCDS, k = b / XCDS;
-    const int per = nblocks / XCDS, rem = nblocks % XCDS;
-    return x * per + min(x, rem) + k;
-}
-
-template <typename S, typename T, int AXI>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occupancy<T>::waves)))
-void k_step(SimDesc d, int force)
-{
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int tile = xcd_block(blockIdx.x, gridDim.x) * WAVES_PER_BLOCK + wave;
-    if (tile >= d.strips * d.segs) return;
-    const Clock* clk = d.clk;
-    if (!force && (clk->status != 0 || clk->accepted >= clk->target)) return;
-    march_tile<S, T, AXI>(d, tile % d.strips, tile / d.strips);
-}
-
-struct TileRef { int sim, strip, seg, pad; };
-
-template <typename S, typename T, int AXI>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occupancy<T>::waves)))
-void k_step_batch(const SimDesc* __restrict__ descs, const TileRef* __restrict__ tiles, int ntiles, int force)
-{
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int tile = xcd_block(blockIdx.x, gridDim.x) * WAVES_PER_BLOCK + wave;
-    if (tile >= ntiles) return;
-    const TileRef tr = tiles[tile];
-    const SimDesc& d = descs[tr.sim];
-    const Clock* clk = d.clk;
-    if (!force && (clk->status != 0 || clk->accepted >= clk->target)) return;
-    march_tile<S, T, AXI>(d, tr.strip, tr.seg);
 }
 
 __global__ void k_bump(Clock* c, long long n)
