@@ -254,38 +254,69 @@ __all__ = ["build", "lib", "roe", "mc", "flux", "make_params", "make_params_si",
            "dry_smax", "taylor_value", "source_g", "ghost", "set_threads", "get_threads", "BC", "GEOM", "Params", "Stats"]
 
 
-def shift(R, M, N, ncols):
+def shift(R, M, N, ncols, fill=None):
     """Move the domain ncols cells along +x1 (the moving domain of Sec. 4):
     column i of the result is column i + ncols of the input; the ncols columns
-    that enter on the right hold undisturbed medium (R = M = N = 0)."""
+    that enter on the right hold undisturbed medium: R = M = N = 0, or, with
+    fill given, the three columns fill(i) returns for new column i."""
     out = []
     for F in (R, M, N):
         G = np.zeros_like(F)
         if ncols < F.shape[1]:
             G[:, : F.shape[1] - ncols] = F[:, ncols:]
         out.append(G)
+    if fill is not None:
+        nx = R.shape[1]
+        for i in range(max(nx - ncols, 0), nx):
+            col = fill(i)
+            for G, c in zip(out, col):
+                G[:, i] = c
     return out[0], out[1], out[2]
 
 
-def run_window(p, R, M, N, nsteps, t, dt, t1, check_every, quantum, x_off=0):
+def _window_params(p, x_off, x0_path):
+    """Parameters of the domain after it moved x_off cells: the Taylor profile
+    is anchored on the path, so in domain coordinates its x0 moves back by
+    x_off (column i of the domain is path column x_off + i)."""
+    q = Params.from_buffer_copy(p)
+    q.taylor_x0 = x0_path - x_off
+    return q
+
+
+def run_window(p, R, M, N, nsteps, t, dt, t1, check_every, quantum, x_off=0, speed=1.0):
     """The two stages of Sec. 4 on a moving domain.  Steps are taken in
     chunks of check_every accepted steps; after each chunk, once t >= t1 (the
-    packet centre has reached the middle of the domain), the domain origin is
-    moved to quantum * floor((t - t1) / quantum) cells (the domain follows
-    the packet at the speed c0 = 1 cell per unit time, in jumps of quantum
-    cells).  Returns (R, M, N, info, x_off)."""
+    wave has reached the middle of the domain), the domain origin is moved to
+    quantum * floor((t - t1) speed / quantum) cells (the domain follows the
+    wave at `speed` cells per unit time -- 1 for c0 -- in jumps of quantum
+    cells).  Analytic (Taylor) data stay on the path: every side uses the
+    profile at path coordinates, and with a Taylor side x+ the entering
+    columns hold the profile at the time of the move.  p's taylor_x0 is the
+    path coordinate of the profile (domain origin at path column x_off on
+    entry).  Returns (R, M, N, info, x_off)."""
     done = 0
     info = None
+    x0_path = p.taylor_x0
+    taylor_right = p.bc[1] == BC["taylor"]
     while done < nsteps:
         k = min(check_every, nsteps - done)
-        R, M, N, info = run(p, R, M, N, k, t=t, dt=dt)
+        q = _window_params(p, x_off, x0_path)
+        R, M, N, info = run(q, R, M, N, k, t=t, dt=dt)
         if info["status"] != OK:
             return R, M, N, info, x_off
         t, dt = info["t"], info["dt_next"]
         done += k
         if k == check_every and t >= t1:
-            target = quantum * int(np.floor((t - t1) / quantum))
+            target = quantum * int(np.floor((t - t1) * speed / quantum))
             if target > x_off:
-                R, M, N = shift(R, M, N, target - x_off)
+                fill = None
+                if taylor_right:
+                    qn = _window_params(p, target, x0_path)
+                    ys = np.arange(p.ny) + 0.5
+
+                    def fill(i, qn=qn, tt=t):
+                        v = np.array([taylor_value(qn, i + 0.5, y, tt) for y in ys])
+                        return v[:, 0], v[:, 1], v[:, 2]
+                R, M, N = shift(R, M, N, target - x_off, fill)
                 x_off = target
     return R, M, N, info, x_off

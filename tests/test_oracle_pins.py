@@ -4,6 +4,8 @@ None of these tests re-types an oracle formula and compares it with itself:
 each checks a property that a dropped term, a wrong sign, a wrong index or a
 transposed operand anywhere in the oracle would break.
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -822,3 +824,66 @@ def test_no_retries_left_keeps_the_state(orc):
     p.max_retries = 1
     _, _, _, info = orc.run(p, R, M, N, 3, dt=dt_bad)
     assert info["status"] == orc.OK and info["steps"] == 3 and info["rejected"] == 1
+
+
+def test_moving_domain_with_taylor_sides_matches_the_fixed_domain(orc):
+    """An oblique Taylor shock (theta_T = pi/8, eq. OurTaylorS rotated) with
+    analytic data on all four sides, run on a domain 96 cells wide that stays
+    still until the front's trace on the middle row reaches the middle column
+    at t1 and then follows it along x1 at the trace speed 1/cos(theta_T) in
+    jumps of 4 cells, must equal, column for column at its current origin, the
+    same run on a fixed domain 200 cells wide with the same rows, except
+    within 20 cells of the trailing edge: there the fixed run holds the waves
+    the front sheds backwards, which the moving domain's analytic side cuts
+    off (the difference dies out within 17 cells).  The data on every side are
+    taken at path coordinates and the entering columns hold the profile (the
+    medium ahead of the front, uniform to the last bit on both runs).  A move
+    in the wrong direction, by the wrong amount, or data anchored on the domain
+    instead of the path fails this."""
+    th = math.pi / 8
+    c, s = math.cos(th), math.sin(th)
+    amp, width, beta = 1e-3, 1.5, 3.5
+    delta = beta * amp * width              # travelling-wave balance of eq. OurTaylorS
+    ny, nxw, nxf = 24, 96, 200
+    xmid = nxw / 2
+    x0 = 24.0                                # front through (x0, 0) at t = 0 (xi = 0)
+    tay = {"amp": amp, "width": width, "x0": x0, "y0": 0.0, "angle": th}
+
+    def params(nx):
+        return orc.make_params(nx, ny, beta, delta, bc=("taylor",) * 4, taylor=tay)
+
+    def state(p, nx):
+        q = np.array([[orc.taylor_value(p, i + 0.5, j + 0.5, 0.0) for i in range(nx)] for j in range(ny)])
+        return q[..., 0], q[..., 1], q[..., 2]
+
+    pf, pw = params(nxf), params(nxw)
+    # trace of the front on the middle row: xi = 0 at x = x0 - y s / c + t / c
+    t1 = (xmid - (x0 - (ny / 2) * s / c)) * c
+    steps = 90
+    Rf, Mf, Nf, i_f = orc.run(pf, *state(pf, nxf), steps)
+    Rw, Mw, Nw, i_w, x_off = orc.run_window(pw, *state(pw, nxw), steps, 0.0, 0.0, t1, 5, 4, speed=1.0 / c)
+    assert i_f["status"] == 0 and i_w["status"] == 0
+    assert i_w["t"] == i_f["t"] and t1 > 5.0 and i_w["t"] > t1 + 40.0
+    assert x_off == 4 * math.floor((i_w["t"] - t1) / c / 4) and x_off >= 40
+    keep = slice(20, nxw)
+    for w_, f_ in ((Rw, Rf), (Mw, Mf), (Nw, Nf)):
+        assert np.max(np.abs(w_[:, keep] - f_[:, x_off:x_off + nxw][:, keep])) <= 1e-13 * amp
+    # the front crosses the middle row inside the compared columns, and the
+    # trailing edge does differ (the comparison is not vacuous there)
+    row = Rw[ny // 2]
+    k = int(np.argmin(np.abs(row)))
+    assert 30 <= k <= nxw - 20 and abs(row[k]) < 0.3 * amp and row[-1] == -amp
+    assert np.max(np.abs(Rw[:, :4] - Rf[:, x_off:x_off + 4])) > 1e-8 * amp
+    # columns entering right after a move hold the profile at their path
+    # coordinates and the time of the move (here near the front, where the
+    # profile is not uniform): one chunk of 5 steps, then the move
+    tay["x0"] = 34.0                          # the front close to the right side
+    pn, pp = params(40), params(nxf)
+    Rn, Mn, Nn, i_n, xo = orc.run_window(pn, *state(pn, 40), 5, 0.0, 0.0, 0.0, 5, 4, speed=2.7)
+    assert i_n["status"] == 0 and xo == 4 * math.floor(i_n["t"] * 2.7 / 4) and 8 <= xo < 40
+    for i in range(40 - xo, 40):
+        for j in range(ny):
+            want = orc.taylor_value(pp, xo + i + 0.5, j + 0.5, i_n["t"])
+            got = np.array([Rn[j, i], Mn[j, i], Nn[j, i]])
+            assert np.max(np.abs(got - want)) <= 1e-15 * amp
+    assert np.min(np.abs(Rn[:, 40 - xo:])) < 0.9 * amp
