@@ -281,6 +281,25 @@ fvna_status fvna_get_stats(fvna_ctx* c, fvna_stats* s);
  * computed on the device in a fixed order (identical on every run). */
 fvna_status fvna_sums(fvna_ctx* c, double out[3]);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the sums of
+ * fvna_sums for one state buffer, with no context, no allocation and no
+ * synchronisation.  p describes the buffer (grid, precision, store_scale,
+ * rho0, c0; validated as by fvna_workspace_size); state is a device buffer
+ * laid out as the library stores a state (fvna_workspace_size's state_bytes:
+ * three planes R, M, N); out is device memory for 3 doubles, which receives
+ * the sums of rho', rho u, rho v in SI, bitwise equal to what fvna_sums
+ * returns for a context whose current state is that buffer.  Enqueued on
+ * hip_stream (NULL = default stream); the result is valid once the stream
+ * has reached it.  The partial sums live in a static device array of the
+ * library, 512 x 3 doubles (12 KiB) per device, whatever the grid size (so
+ * no grid fvna_workspace_size accepts is too large); it is found at the
+ * first call on each device and kept until the process ends.  Every call on
+ * one device uses the same array: calls that overlap on one device (two
+ * streams, two threads) race and give wrong sums.  FVNA_E_INVALID for NULL
+ * or misaligned (not 8-byte) pointers or invalid parameters. */
+fvna_status fvna_sums_noalloc(const fvna_params* p, const void* state, void* hip_stream, double* out);
+
 /* Time `reps` back-to-back launches of the fused step kernel alone on the
  * context's stream with HIP events; *ms_per_launch receives the mean.  The
  * launches recompute the attempt that the next fvna_step would make, so the

@@ -335,13 +335,14 @@ __global__ __launch_bounds__(256) void k_record(SimDesc d, RecDesc r)
 // thread stride and a fixed tree; the final pass sums the NB partials.
 constexpr int SUM_BLOCKS = 512;
 
+// `state` is the buffer to sum, or null for the simulation's current one.
 template <typename S, typename T>
-__global__ __launch_bounds__(256) void k_sums_partial(SimDesc d, double* __restrict__ part)
+__global__ __launch_bounds__(256) void k_sums_partial(SimDesc d, const void* state, double* __restrict__ part)
 {
     __shared__ double sh[3][256];
     const int b = blockIdx.x;
     double acc[3] = {0.0, 0.0, 0.0};
-    const S* base = (const S*)d.buf[d.clk->cur];
+    const S* base = (const S*)(state ? state : d.buf[d.clk->cur]);
     for (int j = b; j < d.ny; j += SUM_BLOCKS)
         for (int i = threadIdx.x; i < d.nx; i += 256)
             for (int f = 0; f < 3; ++f)
@@ -357,7 +358,9 @@ __global__ __launch_bounds__(256) void k_sums_partial(SimDesc d, double* __restr
         for (int f = 0; f < 3; ++f) part[(size_t)b * 3 + f] = sh[f][0];
 }
 
-__global__ __launch_bounds__(256) void k_sums_final(const double* __restrict__ part, double* __restrict__ out)
+// out[f] = (sum of the partials of field f) * factor_f: the SI sums.
+__global__ __launch_bounds__(256) void k_sums_final(const double* __restrict__ part, double* __restrict__ out,
+                                                    double f0, double f1, double f2)
 {
     __shared__ double sh[3][256];
     double acc[3] = {0.0, 0.0, 0.0};
@@ -370,8 +373,11 @@ __global__ __launch_bounds__(256) void k_sums_final(const double* __restrict__ p
             for (int f = 0; f < 3; ++f) sh[f][threadIdx.x] += sh[f][threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0)
-        for (int f = 0; f < 3; ++f) out[f] = sh[f][0];
+    if (threadIdx.x == 0) {
+        out[0] = sh[0][0] * f0;
+        out[1] = sh[1][0] * f1;
+        out[2] = sh[2][0] * f2;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -518,7 +524,7 @@ struct Launcher {
     void (*dry)(const SimDesc&, hipStream_t);
     void (*imp)(const SimDesc&, const double*, int, int, int, double, int, hipStream_t);
     void (*exp)(const SimDesc&, double*, int, int, int, int, int, double, hipStream_t);
-    void (*sums)(const SimDesc&, double*, hipStream_t);
+    void (*sums)(const SimDesc&, const void* state, double* part, double* out, const double* factor, hipStream_t);
     void (*shift)(const SimDesc&, int, hipStream_t);
     void (*record)(const SimDesc&, const RecDesc&, hipStream_t);
 };
@@ -549,9 +555,10 @@ Launcher make_launcher()
         hipLaunchKernelGGL((k_export<S, T>), dim3((ncols + 255) / 256, nrows), dim3(256), 0, s, d, dst, field, row0,
                            nrows, col0, ncols, factor);
     };
-    L.sums = [](const SimDesc& d, double* part, hipStream_t s) {
-        hipLaunchKernelGGL((k_sums_partial<S, T>), dim3(SUM_BLOCKS), dim3(256), 0, s, d, part);
-        hipLaunchKernelGGL(k_sums_final, dim3(1), dim3(256), 0, s, part, part + SUM_BLOCKS * 3);
+    L.sums = [](const SimDesc& d, const void* state, double* part, double* out, const double* factor,
+                hipStream_t s) {
+        hipLaunchKernelGGL((k_sums_partial<S, T>), dim3(SUM_BLOCKS), dim3(256), 0, s, d, state, part);
+        hipLaunchKernelGGL(k_sums_final, dim3(1), dim3(256), 0, s, part, out, factor[0], factor[1], factor[2]);
     };
     L.shift = [](const SimDesc& d, int ncols, hipStream_t s) {
         const int rows = std::min(3 * d.ny, 65535);
@@ -1106,15 +1113,56 @@ fvna_status fvna_sums(fvna_ctx* c, double out[3])
     fvna_status s = fvna_sync(c);
     if (s != FVNA_OK && !is_device_error(s)) return s;
     double* part = (double*)(c->scratch + OFF_PART);
-    c->L.sums(c->d, part, c->stream);
+    double* res = (double*)(c->scratch + OFF_SUMOUT);
+    const double factor[3] = {c->p.rho0, c->p.rho0 * c->p.c0, c->p.rho0 * c->p.c0};
+    c->L.sums(c->d, nullptr, part, res, factor, c->stream);
     HIP_TRY(hipGetLastError());
-    double h[3];
     HIP_TRY(hipStreamSynchronize(c->stream));
-    HIP_TRY(hipMemcpy(h, c->scratch + OFF_SUMOUT, sizeof(h), hipMemcpyDeviceToHost));
-    const fvna_params& p = c->p;
-    out[0] = h[0] * p.rho0;
-    out[1] = h[1] * p.rho0 * p.c0;
-    out[2] = h[2] * p.rho0 * p.c0;
+    HIP_TRY(hipMemcpy(out, res, 3 * sizeof(double), hipMemcpyDeviceToHost));
+    return FVNA_OK;
+}
+
+// Scratch of fvna_sums_noalloc: the partial sums of k_sums_partial, in a
+// static device array rather than caller or library allocations.  Each device
+// holds its own copy at its own address, found once per device with
+// hipGetSymbolAddress and kept in noalloc_ptr (the array's name is not a
+// device address in host code).  Every call on a device shares that copy.
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static __device__ __align__(256) double noalloc_scratch[SUM_BLOCKS * 3];
+static std::mutex g_noalloc_mu;
+static void* g_noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+
+static fvna_status noalloc_ptr(void** ptr)
+{
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(FVNA_E_INVALID, "device index out of range");
+    std::lock_guard<std::mutex> g(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void* p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch)));
+        if (!p) return fail(FVNA_E_HIP, "hipGetSymbolAddress returned no address for the static scratch");
+        g_noalloc_ptr[dev] = p;
+    }
+    *ptr = g_noalloc_ptr[dev];
+    return FVNA_OK;
+}
+
+fvna_status fvna_sums_noalloc(const fvna_params* p, const void* state, void* hip_stream, double* out)
+{
+    if (!state || !out) return fail(FVNA_E_INVALID, "NULL argument");
+    fvna_status s = validate(p);
+    if (s) return s;
+    if (((uintptr_t)state | (uintptr_t)out) % 8) return fail(FVNA_E_INVALID, "state and out must be 8-byte aligned");
+    void* part = nullptr;
+    s = noalloc_ptr(&part);
+    if (s) return s;
+    SimDesc d;
+    fill_desc(d, p, const_cast<void*>(state), const_cast<void*>(state), nullptr, 16);
+    const Launcher L = pick_launcher(p->precision, p->geometry);
+    const double factor[3] = {p->rho0, p->rho0 * p->c0, p->rho0 * p->c0};
+    L.sums(d, state, (double*)part, out, factor, (hipStream_t)hip_stream);
+    HIP_TRY(hipGetLastError());
     return FVNA_OK;
 }
 

@@ -33,7 +33,7 @@ EXPORTS = [
     "fvna_set_state", "fvna_set_clock", "fvna_step", "fvna_sync", "fvna_shift", "fvna_step_window",
     "fvna_set_recorder",
     "fvna_get_state", "fvna_get_window",
-    "fvna_get_stats", "fvna_sums", "fvna_time_step_kernel", "fvna_autotune", "fvna_get_tile_rows",
+    "fvna_get_stats", "fvna_sums", "fvna_sums_noalloc", "fvna_time_step_kernel", "fvna_autotune", "fvna_get_tile_rows",
     "fvna_last_error", "fvna_destroy", "fvna_batch_create", "fvna_batch_set_state",
     "fvna_batch_step", "fvna_batch_sync", "fvna_batch_get_state", "fvna_batch_get_stats",
     "fvna_batch_time_step_kernel", "fvna_batch_destroy",
@@ -113,6 +113,7 @@ def _load():
         "fvna_get_window": (st, [vp, i32, i32, i32, i32, dp, dp, dp]),
         "fvna_get_stats": (st, [vp, P(fvna_stats)]),
         "fvna_sums": (st, [vp, dp]),
+        "fvna_sums_noalloc": (st, [P(fvna_params), vp, vp, vp]),
         "fvna_time_step_kernel": (st, [vp, i32, dp]),
         "fvna_autotune": (st, [vp, P(i32)]),
         "fvna_get_tile_rows": (st, [vp, P(i32)]),
@@ -394,6 +395,14 @@ def make_source(freq, p_surface, focal_length, aperture, ramp_cycles=3.0, envelo
     return fvna_source(float(freq), float(p_surface), float(focal_length), float(aperture),
                        float(ramp_cycles), env, float(packet_cycles), int(stage2_time is not None),
                        float(stage2_time) if stage2_time is not None else 0.0)
+
+
+def fvna_sums_noalloc(params, state, out, stream=None):
+    """FP64 sums of one state buffer (a device tensor laid out as the library
+    stores a state) into `out` (a device float64 tensor of 3 elements), on
+    `stream` (default: torch's current stream); asynchronous."""
+    check(lib.fvna_sums_noalloc(ctypes.byref(params), ctypes.c_void_p(state.data_ptr()),
+                                _stream_handle(stream), ctypes.c_void_p(out.data_ptr())))
 
 
 def sim_from_workload(w, device="cuda:0", precision=None, **over):
