@@ -76,6 +76,8 @@ struct Clock {
 // Everything a wavefront needs to know about its simulation.
 struct SimDesc {
     int nx, ny, pitch, strips, segs, tile_rows;
+    int seg_edge, seg_mid;       // row segments: 0 = uniform tile_rows; else the first and last
+                                 // segment have seg_edge rows, the others seg_mid (seg_bounds)
     long long plane;             // elements per field plane = pitch * ny
     int bc[4];
     int fixed_dt, max_retries;
@@ -524,6 +526,28 @@ __device__ __forceinline__ void bst(Rsrc r, int vo, int so, bf16 x)
 // The fused step of one wavefront tile.
 // ---------------------------------------------------------------------------
 
+// Rows [r0, r1) of row segment `seg`.  Uniform segments of tile_rows rows, or
+// (seg_edge > 0) a first and a last segment of seg_edge rows and seg_mid rows
+// in each of the others: the first and last segment of a strip take the
+// general path (ghost rows, boundary rows in the source), which costs more
+// per row than the lean path, so they are given fewer rows.
+__device__ __forceinline__ void seg_bounds(const SimDesc& d, int seg, int& r0, int& r1)
+{
+    if (d.seg_edge == 0) {
+        r0 = seg * d.tile_rows;
+        r1 = min(r0 + d.tile_rows, d.ny);
+    } else if (seg == 0) {
+        r0 = 0;
+        r1 = d.seg_edge;
+    } else if (seg == d.segs - 1) {
+        r0 = d.ny - d.seg_edge;
+        r1 = d.ny;
+    } else {
+        r0 = d.seg_edge + (seg - 1) * d.seg_mid;
+        r1 = min(r0 + d.seg_mid, d.ny - d.seg_edge);
+    }
+}
+
 // State one lane carries from one x2 row to the next.  Every entry is
 // consumed by the very next row, so two copies alternated by a two-row
 // unrolled loop need no register moves.
@@ -593,8 +617,8 @@ __device__ __forceinline__ void march(const SimDesc& d, int strip, int seg)
     const int nx = d.nx, ny = d.ny;
     const int c0 = strip * OUTW;
     const int col = c0 - HALO + lane;
-    const int r0 = seg * d.tile_rows;
-    const int r1 = min(r0 + d.tile_rows, ny);
+    int r0, r1;
+    seg_bounds(d, seg, r0, r1);
     const Clock* clk = d.clk;
     const double tn = clk->t;
     const T dt = (T)clk->dt;
@@ -993,8 +1017,8 @@ __device__ __forceinline__ void march_tile(const SimDesc& d, int strip, int seg)
 {
     const int c0 = strip * OUTW;
     const bool interior = d.bc[0] == BC_PERIODIC || (c0 - HALO >= 0 && c0 + OUTW + HALO - 1 <= d.nx - 1);
-    const int r0 = seg * d.tile_rows;
-    const int r1 = min(r0 + d.tile_rows, d.ny);
+    int r0, r1;
+    seg_bounds(d, seg, r0, r1);
     const bool lean = r0 >= HALO && r1 + HALO <= d.ny &&
                       (long long)(r1 - r0 + 2 * HALO) * d.pitch * (long long)sizeof(S) < (1ll << 31);
     if (interior) {

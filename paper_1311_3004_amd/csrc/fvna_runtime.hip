@@ -488,6 +488,35 @@ size_t scratch_bytes_of(const fvna_params* p)
     return stage_off_of(p) + align_up(stage_cells_of(p) * sizeof(double), ALIGN);
 }
 
+// Row segments of a grid for a nominal height tr (device side: seg_bounds).
+// The first and last segment of a strip take the general path, which issues
+// more instructions per row than the lean one (FP64: 13% more VALU); they get
+// about FVNA_EDGE_PERMILLE/1000 of tr rows, the others share the rest evenly
+// in segments of at most tr rows.  Small grids keep uniform segments.  With
+// every wavefront resident at once, the slowest tile ends the step: measured
+// step kernel at 100 / 85 / 70 / 55% edge rows, FP64 4096^2 0.275 / 0.271 /
+// 0.261 / 0.263 ms, axisymmetric FP32 8192 x 2048 0.197 / 0.189 / 0.186 /
+// 0.186 ms, FP32 4096^2 unchanged (0.160 ms).
+#ifndef FVNA_EDGE_PERMILLE
+#define FVNA_EDGE_PERMILLE 700
+#endif
+struct Segments { int segs, edge, mid; };
+static Segments segments_of(int ny, int tr)
+{
+    const int e = std::max(8, (int)(((long long)tr * FVNA_EDGE_PERMILLE + 999) / 1000));
+    if (FVNA_EDGE_PERMILLE >= 1000 || ny - 2 * e < tr) return Segments{(ny + tr - 1) / tr, 0, tr};
+    const int m = (ny - 2 * e + tr - 1) / tr;    // >= 1; (m - 1) tr < ny - 2e, so none is empty
+    return Segments{m + 2, e, (ny - 2 * e + m - 1) / m};
+}
+static void set_segments(SimDesc& d, int tr)
+{
+    const Segments g = segments_of(d.ny, tr);
+    d.tile_rows = tr;
+    d.segs = g.segs;
+    d.seg_edge = g.edge;
+    d.seg_mid = g.mid;
+}
+
 // Rows per wavefront segment when none is given: enough segments that the
 // grid's wavefronts fill every resident slot of the device (CUs x 4 SIMDs x
 // the occupancy the step kernel is compiled for) in one round without
@@ -501,6 +530,14 @@ int default_tile_rows(const fvna_params* p, int cu_count)
     const long long per_strip = std::max(1ll, slots / strips);
     long long tr = (p->ny + per_strip - 1) / per_strip;
     tr = std::max(16ll, std::min(tr, 65536ll));
+    // shorter first and last segments: the smallest height whose segments
+    // still fit the slots (at most per_strip of them)
+    if (FVNA_EDGE_PERMILLE < 1000 && per_strip >= 3) {
+        const double f = FVNA_EDGE_PERMILLE / 1000.0;
+        long long t2 = std::max(16ll, (long long)std::ceil(p->ny / (per_strip - 2 + 2 * f)));
+        while (t2 < 65536 && segments_of(p->ny, (int)t2).segs > per_strip) ++t2;
+        tr = t2;
+    }
     return (int)tr;
 }
 
@@ -591,8 +628,7 @@ static void fill_desc(SimDesc& d, const fvna_params* p, void* a, void* b, Clock*
     d.pitch = pitch_of(p);
     d.plane = (long long)d.pitch * (long long)p->ny;
     d.strips = (p->nx + OUTW - 1) / OUTW;
-    d.tile_rows = tile_rows;
-    d.segs = (p->ny + tile_rows - 1) / tile_rows;
+    set_segments(d, tile_rows);
     for (int s = 0; s < 4; ++s) d.bc[s] = p->bc[s];
     d.fixed_dt = p->fixed_dt ? 1 : 0;
     d.max_retries = p->max_retries;
@@ -1212,16 +1248,14 @@ fvna_status fvna_autotune(fvna_ctx* c, int32_t* tile_rows)
     int best_tr = c->d.tile_rows;
     for (int tr : cand) {
         if (tr > 2 * c->p.ny) continue;
-        c->d.tile_rows = tr;
-        c->d.segs = (c->p.ny + tr - 1) / tr;
+        set_segments(c->d, tr);
         double ms = 0.0;
         fvna_status s = fvna_time_step_kernel(c, 1, &ms);       // warm-up
         if (!s) s = fvna_time_step_kernel(c, 5, &ms);
         if (s) return s;
         if (ms < best) { best = ms; best_tr = tr; }
     }
-    c->d.tile_rows = best_tr;
-    c->d.segs = (c->p.ny + best_tr - 1) / best_tr;
+    set_segments(c->d, best_tr);
     // the timing launches left this attempt's speeds in the clock; they are
     // exactly what the next real attempt computes, so nothing to undo
     drop_graph(c);

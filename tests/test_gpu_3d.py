@@ -23,7 +23,8 @@ def _state(nx, ny, nz, seed):
     rng = np.random.default_rng(seed)
     z, y, x = np.meshgrid(np.arange(nz) + 0.5, np.arange(ny) + 0.5, np.arange(nx) + 0.5, indexing="ij")
     a = 2e6 / (MED["rho0"] * MED["c0"] ** 2)
-    R = a * np.exp(-((x - 0.45 * nx) ** 2 + (y - 0.5 * ny) ** 2 + (z - 0.4 * nz) ** 2) / (2 * 3.0 ** 2))
+    sig = max(3.0, min(nx, ny, nz) / 12.0)
+    R = a * np.exp(-((x - 0.45 * nx) ** 2 + (y - 0.5 * ny) ** 2 + (z - 0.4 * nz) ** 2) / (2 * sig ** 2))
     R = R + 0.01 * a * rng.uniform(-1, 1, R.shape)
     M = [c * R for c in (0.3, -0.2, 0.25)]
     return R, M
@@ -59,6 +60,21 @@ def test_3d_step_vs_oracle(precision, fixed, tol):
     assert err <= tol
     if not fixed:
         assert abs(st["t"] * MED["c0"] / DX - info["t"]) <= 1e-12 * info["t"]
+
+
+@pytest.mark.parametrize("precision,fixed,tol", [("f64", True, 1e-12), ("f64", False, 1e-10),
+                                                 ("f32", True, 2e-6), ("f32", False, 2e-6)])
+def test_3d_step_vs_oracle_large(precision, fixed, tol):
+    """128 x 96 x 96 = 1.18 M cells: many wavefronts per sweep and plane, every
+    side kind, FP32 also with the adaptive time step."""
+    shape = (128, 96, 96)
+    _say(f"case: 3-D {shape} {precision} {'fixed' if fixed else 'adaptive'} dt, 2 steps")
+    err, st, info = _run_pair(precision, 2, fixed, shape=shape, seed=21)
+    _say(f"  max rel err {err:.3e}")
+    assert err <= tol
+    if not fixed:
+        rel_t = 1e-12 if precision == "f64" else 1e-7
+        assert abs(st["t"] * MED["c0"] / DX - info["t"]) <= rel_t * info["t"]
 
 
 def test_3d_refuses_bad_parameters():
