@@ -155,13 +155,13 @@ def other_configs(fvna, inputs, steps):
     return out
 
 
-def three_d(n=256, steps=20):
-    """The 3-D step (first version: one kernel per sweep and one for the
-    source, the step decided on the host) on an n^3 FP32 Gaussian pulse
+def three_d(n=256, steps=200):
+    """The 3-D step (fused x1-x2 sweep, x3 sweep, source and a device-side
+    controller, replayed from a HIP graph) on an n^3 FP32 Gaussian pulse
     (sigma 8 cells, 2 MPa, 0.5% noise, seed 5), extrapolating sides: whole
-    steps per second (host clock, one synchronisation per step) and the mean
-    duration of the four kernels of one step (HIP events) against 32 B per
-    cell-update (read and write of four FP32 fields)."""
+    steps per second (host clock around fvna3_step, which waits once at its
+    end) and the mean duration of the three kernels of one step (HIP events)
+    against 32 B per cell-update (read and write of four FP32 fields)."""
     import time
     import numpy as np
     from paper_1311_3004_amd import fvna3d as f3

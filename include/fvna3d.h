@@ -11,9 +11,12 @@
  * FVNA_BC_EXTRAP0, FVNA_BC_REFLECT (fvna.h).  Errors are fvna_status values,
  * with fvna3_last_error() describing the last failing call.
  *
- * First version: one thread per cell, one kernel per sweep and one for the
- * source, the step decided on the host (one stream synchronisation per
- * attempt).
+ * On the device a step is three kernels and a controller: the x1 and x2
+ * sweeps of z-plane tiles fused (lanes along x1, a register march along x2,
+ * every interface solved once), the x3 sweep (a register march along x3),
+ * the source, then the accept/reject decision and the next time step on one
+ * device thread.  Attempts are replayed from a captured HIP graph; the host
+ * waits once per fvna3_step call.
  */
 #ifndef FVNA3D_H
 #define FVNA3D_H
@@ -39,7 +42,9 @@ typedef struct {
 
 typedef struct fvna3_ctx fvna3_ctx;
 
-/* Bytes of each of the three state buffers and of the scratch buffer. */
+/* Bytes of each of the three state buffers (four fields of nz * ny rows,
+ * rows padded to 256 bytes) and of the scratch buffer (device clock and a
+ * staging area of nx * ny * nz doubles). */
 fvna_status fvna3_workspace_size(const fvna3_params* p, size_t* state_bytes, size_t* scratch_bytes);
 
 /* Borrow three device state buffers, a scratch buffer (sizes above) and a HIP
@@ -52,17 +57,19 @@ fvna_status fvna3_create(const fvna3_params* p, void* buf_a, void* buf_b, void* 
 fvna_status fvna3_set_state(fvna3_ctx* c, const double* rho_p, const double* m1, const double* m2,
                             const double* m3);
 
-/* Take nsteps accepted steps (synchronous; rejected attempts are redone with
- * dt * nu_W / nu, at most max_retries in a row).  FVNA_E_NONHYPERBOLIC,
- * FVNA_E_NONFINITE or FVNA_E_RETRIES stop the run with the state of the last
- * accepted step. */
+/* Take nsteps accepted steps and wait for them (rejected attempts are redone
+ * on the device with dt * nu_W / nu, at most max_retries in a row).
+ * FVNA_E_NONHYPERBOLIC, FVNA_E_NONFINITE or FVNA_E_RETRIES stop the run with
+ * the state of the last accepted step; they stay latched (further steps do
+ * nothing and return them) until fvna3_set_state. */
 fvna_status fvna3_step(fvna3_ctx* c, int64_t nsteps);
 
 fvna_status fvna3_get_state(fvna3_ctx* c, double* rho_p, double* m1, double* m2, double* m3);
 fvna_status fvna3_get_stats(fvna3_ctx* c, fvna_stats* st);
 
-/* Mean duration in ms of the four kernels of one attempt (reps attempts back
- * to back with the current dt, state unchanged). */
+/* Mean duration in ms of the three kernels of one attempt without the
+ * controller (reps recomputations back to back of the attempt the next step
+ * makes; the state and the clock are unchanged). */
 fvna_status fvna3_time_step_kernels(fvna3_ctx* c, int32_t reps, double* ms);
 
 /* Thread-local message of the last failing call of this library. */

@@ -7,6 +7,7 @@ SRC = os.path.join(HERE, "csrc", "fvna3d.hip")
 LIB = os.path.join(HERE, "libfvna3d.so")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-mllvm", "-amdgpu-sched-strategy=max-ilp",
          "-Wno-unused-command-line-argument"]
 
 

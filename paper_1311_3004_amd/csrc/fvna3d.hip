@@ -1,7 +1,27 @@
-// Three-dimensional step (the paper's equations in three dimensions): one
-// thread per cell, one kernel per sweep and one for the source; the step is
-// decided on the host.  Every neighbour index goes through the side rule of
-// its axis and is then clamped to the grid, so no access leaves a buffer.
+// fvna3d.hip -- the three-dimensional step (the paper's equations in three
+// dimensions, which Sec. 5 says they allow) and its C ABI (include/fvna3d.h).
+//
+// State (R, M1, M2, M3) = (rho'/rho0, rho u1/(rho0 c0), ...), dimensionless
+// with the mesh spacing as length unit.  One step: x1 sweep -> x2 sweep ->
+// x3 sweep -> source (Godunov splitting, each sweep the high-resolution Roe
+// scheme of Secs. 3.1-3.2 with a second passive shear wave), then the CFL
+// decision of the opening of Sec. 4, all on the device:
+//   k3_sweep12  x1 and x2 sweeps of one z-plane tile: lanes along x1 (the
+//               left cell, the neighbour waves and the right flux over DPP
+//               lane shifts, every x1 interface solved once), a register
+//               march along x2 (every x2 interface solved once);
+//   k3_sweep3   x3 sweep: a register march along x3, one lane per column;
+//   k3_source   7-point Laplacian of each velocity component: x3 neighbours
+//               carried in registers, x1 neighbours over DPP, x2 neighbours
+//               loaded;
+//   k3_ctrl     accept or reject (control_attempt), one thread.
+// Three state buffers X0, X1, X2 and the device clock's cur = c: the sweeps
+// go X[c] -> X[c+1] -> X[c+2], the source X[c+2] -> X[c+1], and an accepted
+// step makes X[c+1] current (indices modulo 3).  Steps are replayed from a
+// captured HIP graph; the host waits once per fvna3_step call.
+// Ghost values follow the side rule of their axis applied to the state of
+// the stage that needs them (Q^n for x1, the x1-swept state for x2, the
+// x2-swept state for x3, the x3-swept state for the source).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -10,253 +30,624 @@
 #include <string>
 
 #include "../../include/fvna3d.h"
+#include "fvna_device.hpp"
+#include "fvna_step.hpp"
+
+using namespace fvna;
 
 namespace {
 
-thread_local std::string g_err3 = "no error";
-
-fvna_status fail3(fvna_status s, const char* msg)
-{
-    g_err3 = msg;
-    return s;
-}
-
-#define HIP3(x)                                                              \
-    do {                                                                     \
-        hipError_t e_ = (x);                                                 \
-        if (e_ != hipSuccess) return fail3(FVNA_E_HIP, hipGetErrorString(e_)); \
-    } while (0)
+constexpr int HALO12 = 2;                      // x1 stencil: two interfaces each side
+constexpr int OUT12 = WAVE - 2 * HALO12;       // 60 output columns per x1-x2 wavefront
 
 struct Desc3 {
-    int n[3];                 // nx, ny, nz
+    int n[3];                  // nx, ny, nz
+    int pitch;                 // elements per x1 row (padded to 256 bytes)
+    int strips12, segs12, rows12;   // x1-x2 tiles: 60-column strips, row segments of rows12
+    int strips64, segs3, planes3;   // x3 and source tiles: 64-column strips, z segments of planes3
+    long long plane;           // elements per field = pitch * ny * nz
     int bc[6];
-    double beta, delta;       // delta~ = delta / (c0 dx)
+    int fixed_dt, max_retries;
+    double beta, delta;        // delta~ = delta / (c0 dx)
+    double cfl_target, cfl_max;
+    void* buf[3];
+    Clock* clk;
 };
 
-struct Red3 {                 // device reduction of one attempt
-    unsigned long long smax_bits;
-    unsigned int flags;       // 1: non-real speeds, 2: non-finite
-    unsigned int pad;
-};
-
-__device__ __forceinline__ size_t cell(const Desc3& d, int i, int j, int k)
-{
-    return ((size_t)k * d.n[1] + j) * d.n[0] + i;
-}
-
-// Map index m along axis a to a real index by the side rule; sign = -1 when
-// the momentum normal to that axis is mirrored.  Clamped afterwards.
-__device__ __forceinline__ int side_map(const Desc3& d, int a, int m, double& sign)
+// Index m along axis a mapped to a stored index by the side rule of that
+// axis; *neg is set when the momentum normal to the axis is mirrored.
+__device__ __forceinline__ int side_map(const Desc3& d, int a, int m, bool& neg)
 {
     const int n = d.n[a];
-    sign = 1.0;
+    neg = false;
     if (m < 0) {
         const int b = d.bc[2 * a];
         if (b == FVNA_BC_PERIODIC) m += n;
-        else if (b == FVNA_BC_REFLECT) { m = -m - 1; sign = -1.0; }
+        else if (b == FVNA_BC_REFLECT) { m = -m - 1; neg = true; }
         else m = 0;
     } else if (m >= n) {
         const int b = d.bc[2 * a + 1];
         if (b == FVNA_BC_PERIODIC) m -= n;
-        else if (b == FVNA_BC_REFLECT) { m = 2 * n - m - 1; sign = -1.0; }
+        else if (b == FVNA_BC_REFLECT) { m = 2 * n - m - 1; neg = true; }
         else m = n - 1;
     }
     return min(max(m, 0), n - 1);
 }
 
+// ---------------------------------------------------------------------------
+// Roe solver of one interface with two tangential momenta (a, b).
+// ---------------------------------------------------------------------------
+template <typename T> struct W4 { T s1, s2, s3, a1, a2, a3, a4, r1a, r2a, r1b, r2b; };
+template <typename T> struct Q4 { T R, n, a, b; };
+
+// Eigenvalues w + c, w - c, w, w; acoustic eigenvectors (1, s, ra, rb) with
+// ra = za (s - 2 zn)/(Zbar^1 (s - w)) (likewise rb), shear eigenvectors
+// (0, 0, 1, 0) and (0, 0, 0, 1); strengths from sum_p alpha^p r^p = Q_R - Q_L.
+// The means are carried as sums of the two sides (every factor 2 cancels).
+// Returns the interface's largest |s| in the form Cfl<T> reduces (FP32 as an
+// excess over 1) and the discriminant in D.
 template <typename T>
-struct Roe4 {
-    T s[4], W[4][4], amdq[4], apdq[4];
-    bool ok;
+__device__ __forceinline__ T roe4(const Q4<T>& L, T unL, T uaL, T ubL, const Q4<T>& R, T unR, T uaR, T ubR,
+                                  T beta, W4<T>& w, T& D)
+{
+    const T Sr = L.R + R.R, Sn = unL + unR, Sa = uaL + uaR, Sb = ubL + ubR;
+    const T h = rcp(T(2) + Sr);
+    const T wv = Sn * h;
+    const T D1 = fma_(wv, wv - Sn, (beta - T(1)) * Sr);
+    D = T(1) + D1;
+    T c, ic;
+    sqrt_pair(D, c, ic);
+    T spd;
+    if constexpr (sizeof(T) == 8) spd = c + abs_(wv);
+    else spd = fma_(D1, rcp(T(1) + c), abs_(wv));
+    w.s1 = wv + c;
+    w.s2 = wv - c;
+    w.s3 = wv;
+    const T hic = h * ic;
+    const T ka = Sa * hic, kb = Sb * hic;
+    const T e1 = w.s1 - Sn, e2 = w.s2 - Sn;
+    w.r1a = ka * e1;
+    w.r2a = -ka * e2;
+    w.r1b = kb * e1;
+    w.r2b = -kb * e2;
+    const T d1 = R.R - L.R, d2 = R.n - L.n, d3 = R.a - L.a, d4 = R.b - L.b;
+    w.a1 = T(0.5) * ic * fma_(-w.s2, d1, d2);
+    w.a2 = d1 - w.a1;
+    w.a3 = fma_(-w.a2, w.r2a, fma_(-w.a1, w.r1a, d3));
+    w.a4 = fma_(-w.a2, w.r2b, fma_(-w.a1, w.r1b, d4));
+    return spd;
+}
+
+// W^p . W^p' of two interfaces for the acoustic families (entries 0, 1).
+template <typename T>
+__device__ __forceinline__ void dots4(const W4<T>& x, const W4<T>& y, T d[2])
+{
+    d[0] = (x.a1 * y.a1) * fma_(x.r1b, y.r1b, fma_(x.r1a, y.r1a, fma_(x.s1, y.s1, T(1))));
+    d[1] = (x.a2 * y.a2) * fma_(x.r2b, y.r2b, fma_(x.r2a, y.r2a, fma_(x.s2, y.s2, T(1))));
+}
+
+// theta = W_up . W / W . W for an acoustic family (no guard: see theta_of).
+template <typename T>
+__device__ __forceinline__ T theta4(T dup, T a, T s, T ra, T rb)
+{
+    return dup * rcp((a * a) * fma_(rb, rb, fma_(ra, ra, fma_(s, s, T(1)))));
+}
+
+// Fluctuations plus limited corrections of one interface (eqs. fluc:m,
+// fluc:p, limiter, fv-hr): Gm = A^- dQ + F~ for the cell on the low side,
+// Gp = A^+ dQ - F~ for the cell on the high side.  lo/hi: products with the
+// interface below/above (entries 0, 1) and that interface's alpha^3, alpha^4
+// (entries 2, 3).  The upwind interface is the one below for s >= 0.
+template <typename T>
+__device__ __forceinline__ void hr_split4(const W4<T>& w, const T lo[4], const T hi[4], T dt, T Gm[4], T Gp[4])
+{
+    const bool n1 = w.s1 < T(0), n2 = w.s2 < T(0), n3 = w.s3 < T(0);
+    const T ps1 = mc_half(theta4(n1 ? hi[0] : lo[0], w.a1, w.s1, w.r1a, w.r1b));
+    const T ps2 = mc_half(theta4(n2 ? hi[1] : lo[1], w.a2, w.s2, w.r2a, w.r2b));
+    const T ps3 = mc_half((n3 ? hi[2] : lo[2]) * rcp(w.a3));
+    const T ps4 = mc_half((n3 ? hi[3] : lo[3]) * rcp(w.a4));
+    const T as1 = abs_(w.s1), as2 = abs_(w.s2), as3 = abs_(w.s3);
+    const T f1 = fma_(-dt, as1, T(1)) * as1, f2 = fma_(-dt, as2, T(1)) * as2, f3 = fma_(-dt, as3, T(1)) * as3;
+    const T c1 = f1 * (ps1 * w.a1), c2 = f2 * (ps2 * w.a2), c3 = f3 * (ps3 * w.a3), c4 = f3 * (ps4 * w.a4);
+    const T m3 = min_(w.s3, T(0));
+    const T e1 = fma_(min_(w.s1, T(0)), w.a1, c1);
+    const T e2 = fma_(min_(w.s2, T(0)), w.a2, c2);
+    const T e3 = fma_(m3, w.a3, c3);
+    const T e4 = fma_(m3, w.a4, c4);
+    const T g1 = fma_(w.s1, w.a1, -e1);
+    const T g2 = fma_(w.s2, w.a2, -e2);
+    const T g3 = fma_(w.s3, w.a3, -e3);
+    const T g4 = fma_(w.s3, w.a4, -e4);
+    Gm[0] = e1 + e2;
+    Gm[1] = fma_(e1, w.s1, e2 * w.s2);
+    Gm[2] = fma_(e1, w.r1a, fma_(e2, w.r2a, e3));
+    Gm[3] = fma_(e1, w.r1b, fma_(e2, w.r2b, e4));
+    Gp[0] = g1 + g2;
+    Gp[1] = fma_(g1, w.s1, g2 * w.s2);
+    Gp[2] = fma_(g1, w.r1a, fma_(g2, w.r2a, g3));
+    Gp[3] = fma_(g1, w.r1b, fma_(g2, w.r2b, g4));
+}
+
+// State carried by a register march from one cell of the marching axis to
+// the next (split-local components: R, normal, tangential a, tangential b).
+template <typename T> struct March4 {
+    Q4<T> q; T un, ua, ub;     // last cell pushed and its velocities
+    W4<T> w;                   // interface below it
+    T lo[4];                   // products of that interface with the one below it, and its alpha^3, alpha^4
+    Q4<T> part;                // previous cell minus dt Gp of its lower interface (awaiting its upper flux)
 };
 
-// Roe decomposition in the normal direction of (R, Mn, Mt1, Mt2): speeds
-// w +- c, w, w; acoustic eigenvectors (1, s, g Zb3, g Zb4) with
-// g = (s - 2 Zb2)/(Zb1 (s - w)); strengths in closed form.
 template <typename T>
-__device__ __forceinline__ void roe4(const T* qL, const T* qR, T beta, Roe4<T>& o)
+__device__ __forceinline__ void march_zero(March4<T>& m)
 {
-    const T q1L = T(1) + qL[0], q1R = T(1) + qR[0];
-    const T Zb1m1 = T(0.5) * (qL[0] + qR[0]);
-    const T Zb1 = T(1) + Zb1m1;
-    const T Zb2 = T(0.5) * (qL[1] / q1L + qR[1] / q1R);
-    const T Zb3 = T(0.5) * (qL[2] / q1L + qR[2] / q1R);
-    const T Zb4 = T(0.5) * (qL[3] / q1L + qR[3] / q1R);
-    const T Phi = T(1) + T(2) * (beta - T(1)) * Zb1m1;
-    const T w = Zb2 / Zb1;
-    const T disc = (Zb2 * Zb2) / (Zb1 * Zb1) - T(2) * (Zb2 * Zb2) / Zb1 + Phi;
-    o.ok = disc > T(0);
-    const T c = sqrt(o.ok ? disc : T(1));
-    o.s[0] = w + c; o.s[1] = w - c; o.s[2] = w; o.s[3] = w;
-    T dq[4];
-    for (int m = 0; m < 4; ++m) dq[m] = qR[m] - qL[m];
-    const T a1 = (dq[1] - o.s[1] * dq[0]) / (o.s[0] - o.s[1]);
-    const T a2 = dq[0] - a1;
-    const T g1 = (o.s[0] - T(2) * Zb2) / (Zb1 * c);
-    const T g2 = (o.s[1] - T(2) * Zb2) / (Zb1 * -c);
-    const T a3 = dq[2] - Zb3 * (a1 * g1 + a2 * g2);
-    const T a4 = dq[3] - Zb4 * (a1 * g1 + a2 * g2);
-    const T r[4][4] = {{T(1), o.s[0], g1 * Zb3, g1 * Zb4},
-                       {T(1), o.s[1], g2 * Zb3, g2 * Zb4},
-                       {T(0), T(0), T(1), T(0)},
-                       {T(0), T(0), T(0), T(1)}};
-    const T al[4] = {a1, a2, a3, a4};
-    for (int m = 0; m < 4; ++m) { o.amdq[m] = T(0); o.apdq[m] = T(0); }
-    for (int p = 0; p < 4; ++p) {
-        const T sm = min(o.s[p], T(0)), sp = max(o.s[p], T(0));
-        for (int m = 0; m < 4; ++m) {
-            o.W[p][m] = al[p] * r[p][m];
-            o.amdq[m] += sm * o.W[p][m];
-            o.apdq[m] += sp * o.W[p][m];
+    const T z = T(0);
+    m.q = {z, z, z, z};
+    m.un = m.ua = m.ub = z;
+    m.w = {z, z, z, z, z, z, z, z, z, z, z};
+    m.lo[0] = m.lo[1] = m.lo[2] = m.lo[3] = z;
+    m.part = {z, z, z, z};
+}
+
+// Push cell v (split-local q) through a march: solve interface v - 1/2,
+// correct interface v - 3/2, and return cell v - 2 completed in `done`.
+// Adds the speed of interface v - 1/2 to acc when `count`.
+template <typename T>
+__device__ __forceinline__ void march_push(const Q4<T>& q, const March4<T>& in, March4<T>& out, T beta, T dt,
+                                           bool count, Cfl<T>& acc, Q4<T>& done)
+{
+    const T ir = rcp(T(1) + q.R);
+    const T un = q.n * ir, ua = q.a * ir, ub = q.b * ir;
+    W4<T> wA;
+    T D;
+    const T spd = roe4(in.q, in.un, in.ua, in.ub, q, un, ua, ub, beta, wA, D);
+    if (count) acc.add(spd, D);
+    T hi[4];
+    dots4(in.w, wA, hi);
+    hi[2] = wA.a3;
+    hi[3] = wA.a4;
+    T Gm[4], Gp[4];
+    hr_split4(in.w, in.lo, hi, dt, Gm, Gp);
+    done.R = fma_(-dt, Gm[0], in.part.R);
+    done.n = fma_(-dt, Gm[1], in.part.n);
+    done.a = fma_(-dt, Gm[2], in.part.a);
+    done.b = fma_(-dt, Gm[3], in.part.b);
+    out.part.R = fma_(-dt, Gp[0], in.q.R);
+    out.part.n = fma_(-dt, Gp[1], in.q.n);
+    out.part.a = fma_(-dt, Gp[2], in.q.a);
+    out.part.b = fma_(-dt, Gp[3], in.q.b);
+    out.q = q;
+    out.un = un; out.ua = ua; out.ub = ub;
+    out.w = wA;
+    out.lo[0] = hi[0];
+    out.lo[1] = hi[1];
+    out.lo[2] = in.w.a3;
+    out.lo[3] = in.w.a4;
+}
+
+// Fold a lane's CFL bookkeeping into the clock (one atomic per wavefront).
+template <typename T>
+__device__ __forceinline__ void cfl_commit(const Desc3& d, const Cfl<T>& acc, bool counted)
+{
+    T m;
+    bool nh, nf;
+    acc.finish(counted, m, nh, nf);
+    const int lane = threadIdx.x & (WAVE - 1);
+    for (int off = 32; off >= 1; off >>= 1) m = max_(m, perm(m, lane ^ off));
+    const bool anyh = __any(nh), anyf = __any(nf);
+    if (lane == 0) {
+        atomicMax(&d.clk->smax_bits, (unsigned long long)__double_as_longlong(cfl_speed<T>(m)));
+        const unsigned fl = (anyh ? FLAG_NONHYP : 0u) | (anyf ? FLAG_NONFINITE : 0u);
+        if (fl) atomicOr(&d.clk->flags, fl);
+    }
+}
+
+__device__ __forceinline__ bool step_owed(const Clock* c, int force)
+{
+    return force || (c->status == 0 && c->accepted < c->target);
+}
+
+// ---------------------------------------------------------------------------
+// x1 and x2 sweeps of one tile: 64 lanes over columns c0 - 2 .. c0 + 61 (the
+// 60 outputs in lanes 2..61), rows r0 .. r1 - 1 of plane k.  Rows r0 - 2 ..
+// r1 + 1 go through the x1 sweep and the x2 march; a row outside the grid is
+// the x1 sweep of the row its side rule names (mirrored rows with M2
+// negated), which is the side rule applied to the x1-swept state.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occupancy<T>::waves)))
+void k3_sweep12(Desc3 d, int force)
+{
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tile = xcd_block(blockIdx.x, gridDim.x) * WAVES_PER_BLOCK + wave;
+    const int ntiles = d.strips12 * d.segs12 * d.n[2];
+    if (tile >= ntiles) return;
+    const Clock* clk = d.clk;
+    if (!step_owed(clk, force)) return;
+    const int strip = tile % d.strips12;
+    const int seg = (tile / d.strips12) % d.segs12;
+    const int k = tile / (d.strips12 * d.segs12);
+    const int nx = d.n[0], ny = d.n[1];
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int col = strip * OUT12 - HALO12 + lane;
+    const int r0 = seg * d.rows12, r1 = min(r0 + d.rows12, ny);
+    const T dt = (T)clk->dt;
+    const int cur = clk->cur;
+    const T* in = (const T*)d.buf[cur];
+    T* out = (T*)d.buf[cur == 2 ? 0 : cur + 1];
+    const T beta = (T)d.beta;
+    const bool perx = d.bc[0] == FVNA_BC_PERIODIC, pery = d.bc[2] == FVNA_BC_PERIODIC;
+    bool xneg;
+    const int scol = side_map(d, 0, col, xneg);
+    const T xs = xneg ? T(-1) : T(1);
+    const size_t pl = (size_t)d.plane;
+    const size_t zoff = (size_t)k * (size_t)ny * (size_t)d.pitch;
+    const bool out_lane = lane >= HALO12 && lane < WAVE - HALO12 && col < nx;
+    Cfl<T> xacc, yacc;
+
+    // x1 sweep of stored row sr (lane-parallel), components (R, M1, M2, M3)
+    // raw Q^n of the row that row v stands for (side rule along x2)
+    auto load_row = [&](int v) -> Q4<T> {
+        bool yneg;
+        const int sr = side_map(d, 1, v, yneg);
+        const size_t o = zoff + (size_t)sr * (size_t)d.pitch + (size_t)scol;
+        return Q4<T>{in[o], in[pl + o], in[2 * pl + o], in[3 * pl + o]};
+    };
+    auto xsweep = [&](Q4<T> q) -> Q4<T> {
+        q.n = xs * q.n;
+        const T ir = rcp(T(1) + q.R);
+        const T un = q.n * ir, ua = q.a * ir, ub = q.b * ir;
+        Q4<T> L;
+        L.R = from_lo(q.R); L.n = from_lo(q.n); L.a = from_lo(q.a); L.b = from_lo(q.b);
+        const T unL = from_lo(un), uaL = from_lo(ua), ubL = from_lo(ub);
+        W4<T> w;
+        T D;
+        const T spd = roe4(L, unL, uaL, ubL, q, un, ua, ub, beta, w, D);
+        xacc.add(spd, D);
+        W4<T> wr;
+        wr.a1 = from_hi(w.a1); wr.s1 = from_hi(w.s1); wr.r1a = from_hi(w.r1a); wr.r1b = from_hi(w.r1b);
+        wr.a2 = from_hi(w.a2); wr.s2 = from_hi(w.s2); wr.r2a = from_hi(w.r2a); wr.r2b = from_hi(w.r2b);
+        T hi[4], lo[4];
+        dots4(w, wr, hi);
+        hi[2] = from_hi(w.a3);
+        hi[3] = from_hi(w.a4);
+        lo[0] = from_lo(hi[0]); lo[1] = from_lo(hi[1]); lo[2] = from_lo(w.a3); lo[3] = from_lo(w.a4);
+        T Gm[4], Gp[4];
+        hr_split4(w, lo, hi, dt, Gm, Gp);
+        Q4<T> o2;
+        o2.R = fma_(-dt, from_hi(Gm[0]) + Gp[0], q.R);
+        o2.n = fma_(-dt, from_hi(Gm[1]) + Gp[1], q.n);
+        o2.a = fma_(-dt, from_hi(Gm[2]) + Gp[2], q.a);
+        o2.b = fma_(-dt, from_hi(Gm[3]) + Gp[3], q.b);
+        return o2;
+    };
+
+    // x2 march over rows v = r0 - 2 .. r1 + 1; components (R, M2, M1, M3)
+    March4<T> A, B;
+    march_zero(A);
+    const int v0 = r0 - HALO12, v1 = r1 + HALO12;
+    auto step_row = [&](int v, const Q4<T>& raw, const March4<T>& mi, March4<T>& mo) {
+        bool yneg;
+        (void)side_map(d, 1, v, yneg);
+        const Q4<T> x = xsweep(raw);
+        Q4<T> q;                                   // split-local for x2: normal = M2
+        q.R = x.R;
+        q.n = yneg ? -x.a : x.a;
+        q.a = x.n;
+        q.b = x.b;
+        const bool cnt = v > v0 && (pery || (v >= 0 && v <= ny));
+        Q4<T> dn;
+        march_push(q, mi, mo, beta, dt, cnt, yacc, dn);
+        const int j = v - 2;
+        if (j >= r0 && out_lane) {
+            const size_t o = zoff + (size_t)j * (size_t)d.pitch + (size_t)col;
+            out[o] = dn.R;
+            out[pl + o] = dn.a;
+            out[2 * pl + o] = dn.n;
+            out[3 * pl + o] = dn.b;
         }
+    };
+    // two rows of loads in flight ahead of the row being swept (rows past
+    // v1 - 1 are clamped by the side rule and never used)
+    Q4<T> p0 = load_row(v0), p1 = load_row(v0 + 1);
+    int v = v0;
+#pragma unroll 1
+    for (; v + 1 < v1; v += 2) {
+        Q4<T> r = p0;
+        p0 = load_row(v + 2);
+        step_row(v, r, A, B);
+        r = p1;
+        p1 = load_row(v + 3);
+        step_row(v + 1, r, B, A);
+    }
+    if (v < v1) step_row(v, p0, A, B);
+
+    // x1 interfaces: lane l's lies between columns col - 1 and col (lane 0
+    // has no left neighbour); x2 interfaces: lanes with exact x1-swept values
+    const bool real_col = perx || (col >= 0 && col < nx);
+    const bool cnt_x = lane >= 1 && (perx || (col >= 0 && col <= nx));
+    const bool cnt_y = lane >= HALO12 && lane < WAVE - HALO12 && real_col;
+    T sx, sy;
+    bool hx, hy, fx, fy;
+    xacc.finish(cnt_x, sx, hx, fx);
+    yacc.finish(cnt_y, sy, hy, fy);
+    T m = max_(sx, sy);
+    for (int off = 32; off >= 1; off >>= 1) m = max_(m, perm(m, lane ^ off));
+    const bool anyh = __any(hx || hy), anyf = __any(fx || fy);
+    if (lane == 0) {
+        atomicMax(&d.clk->smax_bits, (unsigned long long)__double_as_longlong(cfl_speed<T>(m)));
+        const unsigned fl = (anyh ? FLAG_NONHYP : 0u) | (anyf ? FLAG_NONFINITE : 0u);
+        if (fl) atomicOr(&d.clk->flags, fl);
     }
 }
 
+// ---------------------------------------------------------------------------
+// x3 sweep: lane = column strip * 64 + lane, row j, planes k0 .. k1 - 1 of
+// the output; planes k0 - 2 .. k1 + 1 are pushed through the march, those
+// outside the grid by the x3 side rule applied to the x2-swept state.
+// ---------------------------------------------------------------------------
 template <typename T>
-__device__ __forceinline__ T mc3(T th)
+__global__ __launch_bounds__(256) void k3_sweep3(Desc3 d, int force)
 {
-    return max(T(0), min(min(T(0.5) * (T(1) + th), T(2)), T(2) * th));
-}
-
-// F~ at the interface between the waves F and its upwind neighbour per family.
-template <typename T>
-__device__ __forceinline__ void corr(const Roe4<T>& F, const Roe4<T>& lo, const Roe4<T>& hi, T dt, T* out)
-{
-    for (int m = 0; m < 4; ++m) out[m] = T(0);
-    for (int p = 0; p < 4; ++p) {
-        const Roe4<T>& U = F.s[p] < T(0) ? hi : lo;
-        T num = T(0), den = T(0);
-        for (int m = 0; m < 4; ++m) { num += U.W[p][m] * F.W[p][m]; den += F.W[p][m] * F.W[p][m]; }
-        const T th = den == T(0) ? T(0) : num / den;
-        const T as = fabs(F.s[p]);
-        const T coef = T(0.5) * as * (T(1) - dt * as);
-        const T ph = mc3(th);
-        for (int m = 0; m < 4; ++m) out[m] += coef * (ph * F.W[p][m]);
-    }
-}
-
-template <typename T>
-__device__ __forceinline__ void note_speed(const Roe4<T>& F, double& mloc, unsigned& fl)
-{
-    if (!F.ok) fl |= 1u;
-    double m = 0.0;
-    for (int p = 0; p < 4; ++p) m = fmax(m, (double)fabs(F.s[p]));
-    if (!isfinite(m)) fl |= 2u;
-    else mloc = fmax(mloc, m);
-}
-
-// One sweep along axis a: in -> out (4 planes each), dt in cells.
-template <typename T>
-__global__ __launch_bounds__(256) void k3_sweep(Desc3 d, int a, const T* __restrict__ in, T* __restrict__ out,
-                                                T dt, Red3* red)
-{
-    const size_t cells = (size_t)d.n[0] * d.n[1] * d.n[2];
-    double mloc = 0.0;
-    unsigned fl = 0;
-    // grid-stride over the cells, so that each wavefront folds many cells
-    // into its single atomic (one atomic per cell wavefront serialises)
-    for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < cells;
-         id += (size_t)gridDim.x * blockDim.x) {
-        int ix[3];
-        ix[0] = (int)(id % d.n[0]);
-        ix[1] = (int)((id / d.n[0]) % d.n[1]);
-        ix[2] = (int)(id / ((size_t)d.n[0] * d.n[1]));
-        const int b0 = a == 0 ? 1 : 0, b1 = a == 2 ? 1 : 2;
-        const int comp[4] = {0, 1 + a, 1 + b0, 1 + b1};
-        T q[5][4];                                      // cells i-2 .. i+2 along the axis
-        for (int o = -2; o <= 2; ++o) {
-            double sg;
-            int jx[3] = {ix[0], ix[1], ix[2]};
-            jx[a] = side_map(d, a, ix[a] + o, sg);
-            const size_t off = cell(d, jx[0], jx[1], jx[2]);
-            for (int m = 0; m < 4; ++m) q[o + 2][m] = in[(size_t)comp[m] * cells + off];
-            q[o + 2][1] *= (T)sg;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tile = xcd_block(blockIdx.x, gridDim.x) * WAVES_PER_BLOCK + wave;
+    const int ntiles = d.strips64 * d.n[1] * d.segs3;
+    if (tile >= ntiles) return;
+    const Clock* clk = d.clk;
+    if (!step_owed(clk, force)) return;
+    const int strip = tile % d.strips64;
+    const int j = (tile / d.strips64) % d.n[1];
+    const int seg = tile / (d.strips64 * d.n[1]);
+    const int nx = d.n[0], ny = d.n[1], nz = d.n[2];
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int col = strip * WAVE + lane;
+    const int scol = min(col, nx - 1);
+    const int k0 = seg * d.planes3, k1 = min(k0 + d.planes3, nz);
+    const T dt = (T)clk->dt;
+    const int cur = clk->cur;
+    const T* in = (const T*)d.buf[cur == 2 ? 0 : cur + 1];
+    T* out = (T*)d.buf[cur == 0 ? 2 : cur - 1];
+    const T beta = (T)d.beta;
+    const bool perz = d.bc[4] == FVNA_BC_PERIODIC;
+    const size_t pl = (size_t)d.plane;
+    const size_t zstride = (size_t)ny * (size_t)d.pitch;
+    const size_t rowoff = (size_t)j * (size_t)d.pitch + (size_t)scol;
+    Cfl<T> acc;
+    March4<T> A, B;
+    march_zero(A);
+    const int v0 = k0 - 2, v1 = k1 + 2;
+    // raw x2-swept cell of the plane that plane v stands for, split-local
+    // for x3 (normal = M3), the mirror applied
+    auto load_plane = [&](int v) -> Q4<T> {
+        bool zneg;
+        const int sk = side_map(d, 2, v, zneg);
+        const size_t o = (size_t)sk * zstride + rowoff;
+        Q4<T> q{in[o], in[3 * pl + o], in[pl + o], in[2 * pl + o]};
+        if (zneg) q.n = -q.n;
+        return q;
+    };
+    auto step_plane = [&](int v, const Q4<T>& q, const March4<T>& mi, March4<T>& mo) {
+        const bool cnt = v > v0 && (perz || (v >= 0 && v <= nz));
+        Q4<T> dn;
+        march_push(q, mi, mo, beta, dt, cnt, acc, dn);
+        const int kk = v - 2;
+        if (kk >= k0 && col < nx) {
+            const size_t w = (size_t)kk * zstride + (size_t)j * (size_t)d.pitch + (size_t)col;
+            out[w] = dn.R;
+            out[pl + w] = dn.a;
+            out[2 * pl + w] = dn.b;
+            out[3 * pl + w] = dn.n;
         }
-        const T beta = (T)d.beta;
-        Roe4<T> f[4];                                   // interfaces i-3/2, i-1/2, i+1/2, i+3/2
-        for (int m = 0; m < 4; ++m) roe4<T>(q[m], q[m + 1], beta, f[m]);
-        note_speed(f[1], mloc, fl);                     // i-1/2: adjacent to this real cell
-        if (ix[a] == d.n[a] - 1) note_speed(f[2], mloc, fl);   // and the line's last interface
-        T Fl[4], Fr[4];
-        corr(f[1], f[0], f[2], dt, Fl);
-        corr(f[2], f[1], f[3], dt, Fr);
-        const size_t off = cell(d, ix[0], ix[1], ix[2]);
-        for (int m = 0; m < 4; ++m)
-            out[(size_t)comp[m] * cells + off] = q[2][m] - dt * (f[2].amdq[m] + f[1].apdq[m]) - dt * (Fr[m] - Fl[m]);
+    };
+    Q4<T> p0 = load_plane(v0), p1 = load_plane(v0 + 1);
+    int v = v0;
+#pragma unroll 1
+    for (; v + 1 < v1; v += 2) {
+        Q4<T> r = p0;
+        p0 = load_plane(v + 2);
+        step_plane(v, r, A, B);
+        r = p1;
+        p1 = load_plane(v + 3);
+        step_plane(v + 1, r, B, A);
     }
-    // fold the wavefront, one atomic per wavefront
-    for (int off = 32; off >= 1; off >>= 1) mloc = fmax(mloc, __shfl_xor(mloc, off));
-    const bool any_nh = __any(fl & 1u), any_nf = __any(fl & 2u);
-    if ((threadIdx.x & 63) == 0) {
-        atomicMax(&red->smax_bits, (unsigned long long)__double_as_longlong(mloc));
-        if (any_nh || any_nf) atomicOr(&red->flags, (any_nh ? 1u : 0u) | (any_nf ? 2u : 0u));
-    }
+    if (v < v1) step_plane(v, p0, A, B);
+    cfl_commit(d, acc, col < nx);
 }
 
-// Source: M_c += dt delta~ lap(u_c), 7-point, neighbours by the side rules.
+// ---------------------------------------------------------------------------
+// Source (3-D form of eq. fs:source, forward Euler): M_c += dt delta~ lap(u_c),
+// 7-point Laplacian of u_c = M_c / (1 + R), R unchanged.  Lane = column
+// strip * 64 + lane, row j, planes k0 .. k1 - 1.  Neighbours outside the grid
+// by the side rules (mirrored normal velocity).
+// ---------------------------------------------------------------------------
+template <typename T> struct Vel { T u1, u2, u3; };
+
 template <typename T>
-__global__ __launch_bounds__(256) void k3_source(Desc3 d, const T* __restrict__ in, T* __restrict__ out, T dt)
+__global__ __launch_bounds__(256) void k3_source(Desc3 d, int force)
 {
-    const size_t cells = (size_t)d.n[0] * d.n[1] * d.n[2];
-    const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= cells) return;
-    int ix[3];
-    ix[0] = (int)(id % d.n[0]);
-    ix[1] = (int)((id / d.n[0]) % d.n[1]);
-    ix[2] = (int)(id / ((size_t)d.n[0] * d.n[1]));
-    T lap[3], uc[3];
-    const T rc = T(1) / (T(1) + in[id]);
-    for (int m = 0; m < 3; ++m) { uc[m] = in[(size_t)(1 + m) * cells + id] * rc; lap[m] = T(-6) * uc[m]; }
-    for (int a = 0; a < 3; ++a)
-        for (int o = -1; o <= 1; o += 2) {
-            double sg;
-            int jx[3] = {ix[0], ix[1], ix[2]};
-            jx[a] = side_map(d, a, ix[a] + o, sg);
-            const size_t off = cell(d, jx[0], jx[1], jx[2]);
-            const T rn = T(1) / (T(1) + in[off]);
-            for (int m = 0; m < 3; ++m) {
-                T v = in[(size_t)(1 + m) * cells + off] * rn;
-                if (m == a) v *= (T)sg;
-                lap[m] += v;
-            }
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tile = xcd_block(blockIdx.x, gridDim.x) * WAVES_PER_BLOCK + wave;
+    const int ntiles = d.strips64 * d.n[1] * d.segs3;
+    if (tile >= ntiles) return;
+    const Clock* clk = d.clk;
+    if (!step_owed(clk, force)) return;
+    const int strip = tile % d.strips64;
+    const int j = (tile / d.strips64) % d.n[1];
+    const int seg = tile / (d.strips64 * d.n[1]);
+    const int nx = d.n[0], nz = d.n[2];
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int col = strip * WAVE + lane;
+    // lanes past the last column hold the x+ ghost by the side rule (the
+    // lane after the last column is that column's right neighbour)
+    bool oneg;
+    const int scol = side_map(d, 0, col, oneg);
+    const int k0 = seg * d.planes3, k1 = min(k0 + d.planes3, nz);
+    const T dt = (T)clk->dt;
+    const int cur = clk->cur;
+    const T* in = (const T*)d.buf[cur == 0 ? 2 : cur - 1];
+    T* out = (T*)d.buf[cur == 2 ? 0 : cur + 1];
+    const T kd = dt * (T)d.delta;
+    const size_t pl = (size_t)d.plane;
+    const size_t zstride = (size_t)d.n[1] * (size_t)d.pitch;
+    // x neighbours of the edge lanes: lane 0 needs column col - 1, lane 63
+    // column col + 1 (others come over DPP); y neighbours: rows j - 1, j + 1
+    const bool edge = lane == 0 || lane == WAVE - 1;
+    bool eneg = false, ylneg, yhneg;
+    int ecol = scol;
+    if (lane == 0) ecol = side_map(d, 0, col - 1, eneg);
+    else if (lane == WAVE - 1) ecol = side_map(d, 0, col + 1, eneg);
+    const int jl = side_map(d, 1, j - 1, ylneg), jh = side_map(d, 1, j + 1, yhneg);
+    const size_t rowj = (size_t)j * (size_t)d.pitch;
+    // raw cell at element offset o with the mirrored components negated
+    auto raw = [&](size_t o, bool neg1, bool neg2, bool neg3) -> Q4<T> {
+        Q4<T> q{in[o], in[pl + o], in[2 * pl + o], in[3 * pl + o]};
+        if (neg1) q.n = -q.n;
+        if (neg2) q.a = -q.a;
+        if (neg3) q.b = -q.b;
+        return q;
+    };
+    auto vel = [&](const Q4<T>& q) -> Vel<T> {
+        const T ir = rcp(T(1) + q.R);
+        return Vel<T>{q.n * ir, q.a * ir, q.b * ir};
+    };
+    // this lane's cell in plane v (side rule along x3)
+    auto own = [&](int v) -> Q4<T> {
+        bool zneg;
+        const int sk = side_map(d, 2, v, zneg);
+        return raw((size_t)sk * zstride + rowj + (size_t)scol, oneg, false, zneg);
+    };
+    // its x (edge lanes only) and y neighbours in plane v (v inside the grid
+    // when used; clamped otherwise)
+    struct Nb { Q4<T> e, yl, yh; };
+    auto nbrs = [&](int v) -> Nb {
+        const size_t zo = (size_t)min(max(v, 0), nz - 1) * zstride;
+        Nb b;
+        b.e = Q4<T>{T(0), T(0), T(0), T(0)};
+        if (edge) b.e = raw(zo + rowj + (size_t)ecol, eneg, false, false);
+        b.yl = raw(zo + (size_t)jl * (size_t)d.pitch + (size_t)scol, false, ylneg, false);
+        b.yh = raw(zo + (size_t)jh * (size_t)d.pitch + (size_t)scol, false, yhneg, false);
+        return b;
+    };
+    // loads run ahead: this lane's cells two planes, the neighbours one plane
+    Q4<T> q0 = own(k0), q1 = own(k0 + 1);
+    Nb nb = nbrs(k0);
+    Vel<T> ub = vel(own(k0 - 1)), uc = vel(q0);
+#pragma unroll 1
+    for (int k = k0; k < k1; ++k) {
+        const Q4<T> q2 = own(k + 2);
+        const Nb nb1 = nbrs(k + 1);
+        const Vel<T> ua = vel(q1);
+        const Vel<T> e = vel(nb.e), yl = vel(nb.yl), yh = vel(nb.yh);
+        Vel<T> xl, xh;
+        xl.u1 = from_lo(uc.u1); xl.u2 = from_lo(uc.u2); xl.u3 = from_lo(uc.u3);
+        xh.u1 = from_hi(uc.u1); xh.u2 = from_hi(uc.u2); xh.u3 = from_hi(uc.u3);
+        if (lane == 0) xl = e;
+        if (lane == WAVE - 1) xh = e;
+        // the oracle's order: -6 u_c, then x-, x+, y-, y+, z-, z+
+        auto lap = [&](T c, T a0, T a1, T a2, T a3, T a4, T a5) {
+            return ((((((T(-6) * c + a0) + a1) + a2) + a3) + a4) + a5);
+        };
+        const T l1 = lap(uc.u1, xl.u1, xh.u1, yl.u1, yh.u1, ub.u1, ua.u1);
+        const T l2 = lap(uc.u2, xl.u2, xh.u2, yl.u2, yh.u2, ub.u2, ua.u2);
+        const T l3 = lap(uc.u3, xl.u3, xh.u3, yl.u3, yh.u3, ub.u3, ua.u3);
+        if (col < nx) {
+            const size_t o = (size_t)k * zstride + rowj + (size_t)col;
+            out[o] = q0.R;
+            out[pl + o] = fma_(kd, l1, q0.n);
+            out[2 * pl + o] = fma_(kd, l2, q0.a);
+            out[3 * pl + o] = fma_(kd, l3, q0.b);
         }
-    out[id] = in[id];
-    for (int m = 0; m < 3; ++m)
-        out[(size_t)(1 + m) * cells + id] = in[(size_t)(1 + m) * cells + id] + dt * ((T)d.delta * lap[m]);
+        ub = uc;
+        uc = ua;
+        q0 = q1;
+        q1 = q2;
+        nb = nb1;
+    }
+}
+
+__global__ void k3_ctrl(Desc3 d)
+{
+    if (threadIdx.x == 0) control_attempt(d.clk, d.fixed_dt, d.cfl_target, d.cfl_max, d.max_retries, 3);
+}
+
+__global__ void k3_bump(Clock* c, long long n)
+{
+    if (threadIdx.x == 0) c->target += n;
+}
+
+// First time step from the speeds of every interface of the current state in
+// all three directions (the sweeps run with dt = 0, which leaves the state
+// unchanged, so each sweep sees Q^0).
+__global__ void k3_dt0(Desc3 d)
+{
+    if (threadIdx.x != 0) return;
+    Clock* c = d.clk;
+    const double smax = __longlong_as_double((long long)c->smax_bits);
+    const unsigned flags = c->flags;
+    c->smax_bits = 0ull;
+    c->flags = 0u;
+    if (flags & FLAG_NONHYP) { c->status = ST_NONHYP; c->status_step = 0; return; }
+    if ((flags & FLAG_NONFINITE) || !(smax > 0.0) || !(smax <= 1.7976931348623157e308)) {
+        c->status = ST_NONFINITE;
+        c->status_step = 0;
+        return;
+    }
+    c->dt = d.cfl_target / smax;
+}
+
+__global__ void k3_clock(Clock* c, double t, double dt, int cur)
+{
+    if (threadIdx.x != 0) return;
+    Clock h;
+    __builtin_memset(&h, 0, sizeof(h));
+    h.t = t;
+    h.dt = dt;
+    h.cur = cur;
+    *c = h;
+}
+
+// Host doubles (SI, staged) <-> stored dimensionless field; rows r over
+// ny * nz, grid-strided (gridDim.y is at most 65535).
+template <typename T>
+__global__ void k3_import(Desc3 d, const double* __restrict__ src, int field, double denom)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= d.pitch) return;
+    const int rows = d.n[1] * d.n[2];
+    for (int r = blockIdx.y; r < rows; r += gridDim.y) {
+        T* dst = (T*)d.buf[0] + (size_t)field * (size_t)d.plane + (size_t)r * (size_t)d.pitch;
+        dst[i] = i < d.n[0] ? (T)(src[(size_t)r * d.n[0] + i] / denom) : T(0);
+    }
 }
 
 template <typename T>
-__global__ void k3_import(const double* __restrict__ src, T* __restrict__ dst, size_t n, double denom)
+__global__ void k3_export(Desc3 d, double* __restrict__ dst, int field, double factor)
 {
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) dst[i] = (T)(src[i] / denom);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= d.n[0]) return;
+    const int rows = d.n[1] * d.n[2];
+    const T* base = (const T*)d.buf[d.clk->cur] + (size_t)field * (size_t)d.plane;
+    for (int r = blockIdx.y; r < rows; r += gridDim.y)
+        dst[(size_t)r * d.n[0] + i] = (double)base[(size_t)r * (size_t)d.pitch + i] * factor;
 }
 
-template <typename T>
-__global__ void k3_export(const T* __restrict__ src, double* __restrict__ dst, size_t n, double factor)
+thread_local std::string g_err3 = "no error";
+
+fvna_status fail3(fvna_status s, const std::string& msg)
 {
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) dst[i] = (double)src[i] * factor;
+    g_err3 = msg;
+    return s;
 }
 
-}  // namespace
+#define HIP3(x)                                                                        \
+    do {                                                                               \
+        hipError_t e_ = (x);                                                           \
+        if (e_ != hipSuccess) return fail3(FVNA_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    } while (0)
 
-struct fvna3_ctx {
-    fvna3_params p;
-    Desc3 d;
-    char* buf[3];
-    Red3* red;
-    double* stage;
-    hipStream_t s;
-    int cur = 0;              // buffer holding Q^n
-    double t = 0.0, dt = 0.0, nu_last = 0.0, nu_sum = 0.0, nu_sum2 = 0.0;
-    long long steps = 0, rejected = 0;
-    size_t cells = 0;
-};
-
-namespace {
+constexpr int GRAPH3_CHUNK = 32;    // attempts per captured graph
 
 size_t elem(const fvna3_params* p) { return p->precision == FVNA_F64 ? 8 : 4; }
+int pitch3(const fvna3_params* p) { const int per = 256 / (int)elem(p); return (p->nx + per - 1) / per * per; }
 
 fvna_status validate3(const fvna3_params* p)
 {
@@ -277,38 +668,121 @@ fvna_status validate3(const fvna3_params* p)
     return FVNA_OK;
 }
 
-// One attempt from buf[cur] with dt (cells): x -> y -> z -> source into the
-// last free buffer; returns smax and the flags.
-template <typename T>
-fvna_status attempt3(fvna3_ctx* c, double dt, int* out_buf, double* smax, unsigned* flags)
+// scratch layout: [Clock][staging of one field]
+constexpr size_t OFF3_STAGE = 256;
+
+int cu_count3()
 {
-    const int a = c->cur, b = (a + 1) % 3, e = (a + 2) % 3;
-    T* A = (T*)c->buf[a];
-    T* B = (T*)c->buf[b];
-    T* E = (T*)c->buf[e];
-    HIP3(hipMemsetAsync(c->red, 0, sizeof(Red3), c->s));
-    const int blocks = (int)((c->cells + 255) / 256);
-    const int sweep_blocks = std::min(blocks, 4096);
-    hipLaunchKernelGGL(k3_sweep<T>, dim3(sweep_blocks), dim3(256), 0, c->s, c->d, 0, A, B, (T)dt, c->red);
-    hipLaunchKernelGGL(k3_sweep<T>, dim3(sweep_blocks), dim3(256), 0, c->s, c->d, 1, B, E, (T)dt, c->red);
-    hipLaunchKernelGGL(k3_sweep<T>, dim3(sweep_blocks), dim3(256), 0, c->s, c->d, 2, E, B, (T)dt, c->red);
-    hipLaunchKernelGGL(k3_source<T>, dim3(blocks), dim3(256), 0, c->s, c->d, B, E, (T)dt);
-    HIP3(hipGetLastError());
-    Red3 h;
-    HIP3(hipMemcpyAsync(&h, c->red, sizeof(Red3), hipMemcpyDeviceToHost, c->s));
-    HIP3(hipStreamSynchronize(c->s));
-    *out_buf = e;
-    double m;
-    std::memcpy(&m, &h.smax_bits, sizeof(double));
-    *smax = m;
-    *flags = h.flags;
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) return 256;
+    return n;
+}
+
+// Segment lengths: enough tiles to fill every wavefront slot of the device
+// once (CUs x 4 SIMDs x `waves`) where the grid allows, never shorter than 16
+// cells (the two warm-up cells at each end are repeated work).
+int seg_len(long long tiles_per_seg_unit, int n, int cus, int waves)
+{
+    const long long slots = (long long)cus * 4 * waves;
+    const long long per = std::max(1ll, slots / std::max(1ll, tiles_per_seg_unit));
+    const long long len = (n + per - 1) / per;
+    return (int)std::max(16ll, std::min(len, (long long)n));
+}
+
+}  // namespace
+
+struct fvna3_ctx {
+    fvna3_params p;
+    Desc3 d;
+    hipStream_t s;
+    hipStream_t cap;
+    char* scratch;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void (*launch)(const Desc3&, int force, hipStream_t) = nullptr;
+};
+
+namespace {
+
+template <typename T>
+void launch_sweeps(const Desc3& d, int force, hipStream_t s, bool source)
+{
+    const int t12 = d.strips12 * d.segs12 * d.n[2];
+    const int t3 = d.strips64 * d.n[1] * d.segs3;
+    hipLaunchKernelGGL(k3_sweep12<T>, dim3((t12 + 3) / 4), dim3(256), 0, s, d, force);
+    hipLaunchKernelGGL(k3_sweep3<T>, dim3((t3 + 3) / 4), dim3(256), 0, s, d, force);
+    if (source) hipLaunchKernelGGL(k3_source<T>, dim3((t3 + 3) / 4), dim3(256), 0, s, d, force);
+}
+
+template <typename T>
+void launch_attempt(const Desc3& d, int force, hipStream_t s)
+{
+    launch_sweeps<T>(d, force, s, true);
+    hipLaunchKernelGGL(k3_ctrl, dim3(1), dim3(64), 0, s, d);
+}
+
+void drop_graph3(fvna3_ctx* c)
+{
+    if (c->exec || c->graph) (void)hipStreamSynchronize(c->s);
+    if (c->exec) (void)hipGraphExecDestroy(c->exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->exec = nullptr;
+    c->graph = nullptr;
+}
+
+fvna_status build_graph3(fvna3_ctx* c)
+{
+    if (c->exec) return FVNA_OK;
+    HIP3(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < GRAPH3_CHUNK; ++k) c->launch(c->d, 0, c->cap);
+    hipGraph_t g = nullptr;
+    HIP3(hipStreamEndCapture(c->cap, &g));
+    c->graph = g;
+    HIP3(hipGraphInstantiate(&c->exec, g, nullptr, nullptr, 0));
     return FVNA_OK;
 }
 
-fvna_status attempt_any(fvna3_ctx* c, double dt, int* out_buf, double* smax, unsigned* flags)
+fvna_status enqueue3(fvna3_ctx* c, long long attempts)
 {
-    return c->p.precision == FVNA_F64 ? attempt3<double>(c, dt, out_buf, smax, flags)
-                                      : attempt3<float>(c, dt, out_buf, smax, flags);
+    fvna_status s = build_graph3(c);
+    if (s) return s;
+    for (long long k = 0; k < attempts / GRAPH3_CHUNK; ++k) HIP3(hipGraphLaunch(c->exec, c->s));
+    for (long long k = 0; k < attempts % GRAPH3_CHUNK; ++k) c->launch(c->d, 0, c->s);
+    HIP3(hipGetLastError());
+    return FVNA_OK;
+}
+
+fvna_status read_clock3(fvna3_ctx* c, Clock* h)
+{
+    HIP3(hipStreamSynchronize(c->s));
+    HIP3(hipMemcpy(h, c->d.clk, sizeof(Clock), hipMemcpyDeviceToHost));
+    return FVNA_OK;
+}
+
+fvna_status status3(int st)
+{
+    switch (st) {
+    case 0: return FVNA_OK;
+    case ST_NONHYP: return fail3(FVNA_E_NONHYPERBOLIC, "non-real Roe speeds (discriminant <= 0) in a step");
+    case ST_NONFINITE: return fail3(FVNA_E_NONFINITE, "non-finite wave speed in a step");
+    case ST_RETRIES: return fail3(FVNA_E_RETRIES, "too many rejected attempts in a row");
+    default: return fail3(FVNA_E_STATE, "unknown device status");
+    }
+}
+
+// Wait for the stream and top up the steps rejected attempts left owed.
+fvna_status sync3(fvna3_ctx* c)
+{
+    Clock h;
+    for (int guard = 0; guard < 1000; ++guard) {
+        fvna_status s = read_clock3(c, &h);
+        if (s) return s;
+        if (h.status != 0 || h.accepted >= h.target) return status3(h.status);
+        s = enqueue3(c, h.target - h.accepted);
+        if (s) return s;
+    }
+    return fail3(FVNA_E_STATE, "steps still owed after many top-up rounds");
 }
 
 }  // namespace
@@ -322,30 +796,70 @@ fvna_status fvna3_workspace_size(const fvna3_params* p, size_t* state_bytes, siz
     fvna_status s = validate3(p);
     if (s) return s;
     if (!state_bytes || !scratch_bytes) return fail3(FVNA_E_INVALID, "NULL argument");
-    const size_t cells = (size_t)p->nx * p->ny * p->nz;
-    *state_bytes = 4 * cells * elem(p);
-    *scratch_bytes = 256 + cells * sizeof(double);
+    *state_bytes = 4 * (size_t)pitch3(p) * (size_t)p->ny * (size_t)p->nz * elem(p);
+    *scratch_bytes = OFF3_STAGE + (size_t)p->nx * (size_t)p->ny * (size_t)p->nz * sizeof(double);
     return FVNA_OK;
 }
 
 fvna_status fvna3_create(const fvna3_params* p, void* buf_a, void* buf_b, void* buf_c, void* scratch, void* stream,
                          fvna3_ctx** out)
 {
+    if (!out) return fail3(FVNA_E_INVALID, "out is NULL");
+    *out = nullptr;
     fvna_status s = validate3(p);
     if (s) return s;
-    if (!buf_a || !buf_b || !buf_c || !scratch || !out) return fail3(FVNA_E_INVALID, "NULL buffer");
+    if (!buf_a || !buf_b || !buf_c || !scratch) return fail3(FVNA_E_INVALID, "NULL buffer");
+    if (((uintptr_t)buf_a | (uintptr_t)buf_b | (uintptr_t)buf_c | (uintptr_t)scratch) % 256)
+        return fail3(FVNA_E_INVALID, "device buffers must be 256-byte aligned");
     fvna3_ctx* c = new (std::nothrow) fvna3_ctx;
     if (!c) return fail3(FVNA_E_NOMEM, "out of host memory");
     c->p = *p;
-    c->d.n[0] = p->nx; c->d.n[1] = p->ny; c->d.n[2] = p->nz;
-    for (int k = 0; k < 6; ++k) c->d.bc[k] = p->bc[k];
-    c->d.beta = p->beta;
-    c->d.delta = p->delta / (p->c0 * p->dx);
-    c->buf[0] = (char*)buf_a; c->buf[1] = (char*)buf_b; c->buf[2] = (char*)buf_c;
-    c->red = (Red3*)scratch;
-    c->stage = (double*)((char*)scratch + 256);
+    Desc3& d = c->d;
+    std::memset(&d, 0, sizeof(d));
+    d.n[0] = p->nx; d.n[1] = p->ny; d.n[2] = p->nz;
+    d.pitch = pitch3(p);
+    d.plane = (long long)d.pitch * p->ny * p->nz;
+    const int cus = cu_count3();
+    // resident waves per SIMD the kernels' registers allow: FP32 5-6, FP64 3-4
+#ifndef FVNA3_WAVES
+#define FVNA3_WAVES 4
+#endif
+    const int waves = p->precision == FVNA_F64 ? 2 : FVNA3_WAVES;
+    d.strips12 = (p->nx + OUT12 - 1) / OUT12;
+    d.rows12 = seg_len((long long)d.strips12 * p->nz, p->ny, cus, waves);
+    d.segs12 = (p->ny + d.rows12 - 1) / d.rows12;
+    d.strips64 = (p->nx + WAVE - 1) / WAVE;
+    d.planes3 = seg_len((long long)d.strips64 * p->ny, p->nz, cus, waves);
+    d.segs3 = (p->nz + d.planes3 - 1) / d.planes3;
+    for (int k = 0; k < 6; ++k) d.bc[k] = p->bc[k];
+    d.fixed_dt = p->fixed_dt ? 1 : 0;
+    d.max_retries = p->max_retries;
+    d.beta = p->beta;
+    d.delta = p->delta / (p->c0 * p->dx);
+    d.cfl_target = p->cfl_target;
+    d.cfl_max = p->cfl_max;
+    d.buf[0] = buf_a; d.buf[1] = buf_b; d.buf[2] = buf_c;
+    d.clk = (Clock*)scratch;
+    c->scratch = (char*)scratch;
     c->s = (hipStream_t)stream;
-    c->cells = (size_t)p->nx * p->ny * p->nz;
+    c->launch = p->precision == FVNA_F64 ? launch_attempt<double> : launch_attempt<float>;
+    if (hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess) {
+        delete c;
+        return fail3(FVNA_E_HIP, "cannot create the capture stream");
+    }
+    const size_t sb = 4 * (size_t)d.plane * elem(p);
+    for (int b = 0; b < 3; ++b)
+        if (hipMemsetAsync(d.buf[b], 0, sb, c->s) != hipSuccess) {
+            (void)hipStreamDestroy(c->cap);
+            delete c;
+            return fail3(FVNA_E_HIP, "cannot clear the state buffers");
+        }
+    hipLaunchKernelGGL(k3_clock, dim3(1), dim3(64), 0, c->s, d.clk, 0.0, 0.0, 0);
+    if (hipStreamSynchronize(c->s) != hipSuccess) {
+        (void)hipStreamDestroy(c->cap);
+        delete c;
+        return fail3(FVNA_E_HIP, "cannot initialise the clock");
+    }
     *out = c;
     return FVNA_OK;
 }
@@ -354,29 +868,35 @@ fvna_status fvna3_set_state(fvna3_ctx* c, const double* rho_p, const double* m1,
 {
     if (!c || !rho_p || !m1 || !m2 || !m3) return fail3(FVNA_E_INVALID, "NULL argument");
     const fvna3_params& p = c->p;
+    const Desc3& d = c->d;
     const double* src[4] = {rho_p, m1, m2, m3};
     const double denom[4] = {p.rho0, p.rho0 * p.c0, p.rho0 * p.c0, p.rho0 * p.c0};
-    const size_t n = c->cells, es = elem(&p);
-    const int blocks = (int)((n + 255) / 256);
+    const size_t n = (size_t)p.nx * p.ny * p.nz;
+    double* stage = (double*)(c->scratch + OFF3_STAGE);
+    HIP3(hipStreamSynchronize(c->s));
+    const dim3 grid((d.pitch + 255) / 256, std::min(p.ny * p.nz, 65535));
     for (int f = 0; f < 4; ++f) {
-        HIP3(hipMemcpyAsync(c->stage, src[f], n * sizeof(double), hipMemcpyHostToDevice, c->s));
-        char* dst = c->buf[0] + (size_t)f * n * es;
-        if (p.precision == FVNA_F64) hipLaunchKernelGGL(k3_import<double>, dim3(blocks), dim3(256), 0, c->s, c->stage, (double*)dst, n, denom[f]);
-        else hipLaunchKernelGGL(k3_import<float>, dim3(blocks), dim3(256), 0, c->s, c->stage, (float*)dst, n, denom[f]);
+        HIP3(hipMemcpyAsync(stage, src[f], n * sizeof(double), hipMemcpyHostToDevice, c->s));
+        if (p.precision == FVNA_F64) hipLaunchKernelGGL(k3_import<double>, grid, dim3(256), 0, c->s, d, stage, f, denom[f]);
+        else hipLaunchKernelGGL(k3_import<float>, grid, dim3(256), 0, c->s, d, stage, f, denom[f]);
+        HIP3(hipGetLastError());
+        HIP3(hipStreamSynchronize(c->s));
+    }
+    const double dt0 = p.dt0 > 0 ? p.dt0 * p.c0 / p.dx : 0.0;
+    hipLaunchKernelGGL(k3_clock, dim3(1), dim3(64), 0, c->s, d.clk, 0.0, dt0, 0);
+    HIP3(hipGetLastError());
+    if (!(dt0 > 0)) {
+        // dt = 0: the x1, x2 and x3 sweeps see Q^0 (the source is not needed)
+        if (p.precision == FVNA_F64) launch_sweeps<double>(d, 1, c->s, false);
+        else launch_sweeps<float>(d, 1, c->s, false);
+        hipLaunchKernelGGL(k3_dt0, dim3(1), dim3(64), 0, c->s, d);
         HIP3(hipGetLastError());
     }
-    HIP3(hipStreamSynchronize(c->s));
-    c->cur = 0; c->t = 0.0; c->steps = 0; c->rejected = 0; c->nu_last = c->nu_sum = c->nu_sum2 = 0.0;
-    if (p.dt0 > 0) {
-        c->dt = p.dt0 * p.c0 / p.dx;
-        return FVNA_OK;
-    }
-    int ob; double smax; unsigned fl;
-    fvna_status s = attempt_any(c, 0.0, &ob, &smax, &fl);   // dt = 0: speeds of Q^0 in all three sweeps
+    Clock h;
+    fvna_status s = read_clock3(c, &h);
     if (s) return s;
-    if (fl & 1u) return fail3(FVNA_E_NONHYPERBOLIC, "non-real Roe speeds in the initial state");
-    if ((fl & 2u) || !(smax > 0)) return fail3(FVNA_E_NONFINITE, "no finite positive wave speed in the initial state");
-    c->dt = p.cfl_target / smax;
+    if (h.status == ST_NONHYP) return fail3(FVNA_E_NONHYPERBOLIC, "non-real Roe speeds in the initial state");
+    if (h.status) return fail3(FVNA_E_NONFINITE, "no finite positive wave speed in the initial state");
     return FVNA_OK;
 }
 
@@ -384,46 +904,30 @@ fvna_status fvna3_step(fvna3_ctx* c, int64_t nsteps)
 {
     if (!c) return fail3(FVNA_E_INVALID, "ctx is NULL");
     if (nsteps < 0) return fail3(FVNA_E_INVALID, "nsteps must be >= 0");
-    int retries = 0;
-    for (int64_t k = 0; k < nsteps;) {
-        int ob; double smax; unsigned fl;
-        fvna_status s = attempt_any(c, c->dt, &ob, &smax, &fl);
-        if (s) return s;
-        if (fl & 1u) return fail3(FVNA_E_NONHYPERBOLIC, "non-real Roe speeds in a step");
-        if (fl & 2u) return fail3(FVNA_E_NONFINITE, "non-finite wave speed in a step");
-        const double nu = c->dt * smax;
-        c->nu_last = nu;
-        if (!c->p.fixed_dt && nu > c->p.cfl_max) {
-            c->rejected++;
-            if (++retries > c->p.max_retries) return fail3(FVNA_E_RETRIES, "too many rejected attempts in a row");
-            c->dt *= c->p.cfl_target / nu;
-            continue;
-        }
-        retries = 0;
-        c->cur = ob;
-        c->t += c->dt;
-        c->steps++;
-        ++k;
-        c->nu_sum += nu; c->nu_sum2 += nu * nu;
-        if (!c->p.fixed_dt) c->dt *= c->p.cfl_target / nu;
-    }
-    return FVNA_OK;
+    if (nsteps == 0) return FVNA_OK;
+    hipLaunchKernelGGL(k3_bump, dim3(1), dim3(64), 0, c->s, c->d.clk, (long long)nsteps);
+    HIP3(hipGetLastError());
+    fvna_status s = enqueue3(c, nsteps);
+    if (s) return s;
+    return sync3(c);
 }
 
 fvna_status fvna3_get_state(fvna3_ctx* c, double* rho_p, double* m1, double* m2, double* m3)
 {
     if (!c || !rho_p || !m1 || !m2 || !m3) return fail3(FVNA_E_INVALID, "NULL argument");
     const fvna3_params& p = c->p;
+    const Desc3& d = c->d;
     double* dst[4] = {rho_p, m1, m2, m3};
     const double fac[4] = {p.rho0, p.rho0 * p.c0, p.rho0 * p.c0, p.rho0 * p.c0};
-    const size_t n = c->cells, es = elem(&p);
-    const int blocks = (int)((n + 255) / 256);
+    const size_t n = (size_t)p.nx * p.ny * p.nz;
+    double* stage = (double*)(c->scratch + OFF3_STAGE);
+    HIP3(hipStreamSynchronize(c->s));
+    const dim3 grid((p.nx + 255) / 256, std::min(p.ny * p.nz, 65535));
     for (int f = 0; f < 4; ++f) {
-        const char* src = c->buf[c->cur] + (size_t)f * n * es;
-        if (p.precision == FVNA_F64) hipLaunchKernelGGL(k3_export<double>, dim3(blocks), dim3(256), 0, c->s, (const double*)src, c->stage, n, fac[f]);
-        else hipLaunchKernelGGL(k3_export<float>, dim3(blocks), dim3(256), 0, c->s, (const float*)src, c->stage, n, fac[f]);
+        if (p.precision == FVNA_F64) hipLaunchKernelGGL(k3_export<double>, grid, dim3(256), 0, c->s, d, stage, f, fac[f]);
+        else hipLaunchKernelGGL(k3_export<float>, grid, dim3(256), 0, c->s, d, stage, f, fac[f]);
         HIP3(hipGetLastError());
-        HIP3(hipMemcpyAsync(dst[f], c->stage, n * sizeof(double), hipMemcpyDeviceToHost, c->s));
+        HIP3(hipMemcpyAsync(dst[f], stage, n * sizeof(double), hipMemcpyDeviceToHost, c->s));
         HIP3(hipStreamSynchronize(c->s));
     }
     return FVNA_OK;
@@ -432,45 +936,44 @@ fvna_status fvna3_get_state(fvna3_ctx* c, double* rho_p, double* m1, double* m2,
 fvna_status fvna3_get_stats(fvna3_ctx* c, fvna_stats* st)
 {
     if (!c || !st) return fail3(FVNA_E_INVALID, "NULL argument");
+    Clock h;
+    fvna_status s = read_clock3(c, &h);
+    if (s) return s;
     const double tu = c->p.dx / c->p.c0;
     std::memset(st, 0, sizeof(*st));
-    st->t = c->t * tu;
-    st->dt_next = c->dt * tu;
-    st->nu_last = c->nu_last;
-    if (c->steps) {
-        st->nu_mean = c->nu_sum / c->steps;
-        const double v = c->nu_sum2 / c->steps - st->nu_mean * st->nu_mean;
-        st->nu_std = v > 0 ? std::sqrt(v) : 0.0;
-    }
-    st->steps = c->steps;
-    st->rejected = c->rejected;
-    st->status = FVNA_OK;
+    st->t = h.t * tu;
+    st->dt_next = h.dt * tu;
+    st->nu_last = h.nu_last;
+    st->nu_mean = h.nu_mean;
+    st->nu_std = h.nu_count > 0 ? std::sqrt(h.nu_m2 / (double)h.nu_count) : 0.0;
+    st->steps = h.accepted;
+    st->rejected = h.rejected;
+    st->status = h.status;
+    st->status_step = h.status_step;
     return FVNA_OK;
 }
 
 fvna_status fvna3_time_step_kernels(fvna3_ctx* c, int32_t reps, double* ms)
 {
     if (!c || !ms || reps < 1) return fail3(FVNA_E_INVALID, "bad argument");
+    // back-to-back recomputations of the attempt the next step would make
+    // (forced, no controller): the state and the clock are unchanged apart
+    // from the attempt's speed maximum, which the next controller run clears
+    auto sweeps = c->p.precision == FVNA_F64 ? launch_sweeps<double> : launch_sweeps<float>;
     hipEvent_t e0, e1;
     HIP3(hipEventCreate(&e0));
     HIP3(hipEventCreate(&e1));
-    int ob; double smax; unsigned fl;
-    fvna_status s = attempt_any(c, c->dt, &ob, &smax, &fl);       // warm-up
-    if (s) return s;
-    float total = 0.0f;
-    for (int r = 0; r < reps; ++r) {
-        HIP3(hipEventRecord(e0, c->s));
-        s = attempt_any(c, c->dt, &ob, &smax, &fl);
-        if (s) return s;
-        HIP3(hipEventRecord(e1, c->s));
-        HIP3(hipEventSynchronize(e1));
-        float t = 0.0f;
-        HIP3(hipEventElapsedTime(&t, e0, e1));
-        total += t;
-    }
+    sweeps(c->d, 1, c->s, true);
+    HIP3(hipEventRecord(e0, c->s));
+    for (int r = 0; r < reps; ++r) sweeps(c->d, 1, c->s, true);
+    HIP3(hipGetLastError());
+    HIP3(hipEventRecord(e1, c->s));
+    HIP3(hipEventSynchronize(e1));
+    float t = 0.0f;
+    HIP3(hipEventElapsedTime(&t, e0, e1));
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    *ms = total / reps;
+    *ms = (double)t / reps;
     return FVNA_OK;
 }
 
@@ -478,6 +981,8 @@ void fvna3_destroy(fvna3_ctx* c)
 {
     if (!c) return;
     (void)hipStreamSynchronize(c->s);
+    drop_graph3(c);
+    (void)hipStreamDestroy(c->cap);
     delete c;
 }
 

@@ -73,6 +73,52 @@ struct Clock {
     double pad;
 };
 
+// Accept or reject the attempt just made, from its largest wave speed (the
+// CFL rule of the opening of Sec. 4; rejection as stated in include/fvna.h):
+// nu = dt max|s|; nu > cfl_max rejects (state kept, dt *= nu_W/nu, at most
+// max_retries in a row), otherwise the step is accepted, t += dt, the buffer
+// holding the new state (cur + 1 modulo nbuf) becomes current and, unless
+// the time step is fixed, dt *= nu_W/nu.  All memory traffic is issued at
+// once, so the launch costs one round trip: the attempt's largest speed and
+// flags are taken (and cleared for the next attempt) whether or not the
+// attempt counts -- a step launch that had nothing to do left them at zero.
+__device__ __forceinline__ void control_attempt(Clock* c, int fixed_dt, double cfl_target, double cfl_max,
+                                                int max_retries, int nbuf)
+{
+    const unsigned long long sb = atomicExch(&c->smax_bits, 0ull);
+    const unsigned flags = atomicExch(&c->flags, 0u);
+    const Clock h = *c;
+    if (h.status != 0 || h.accepted >= h.target) return;
+    const double smax = __longlong_as_double((long long)sb);
+    c->attempts = h.attempts + 1;
+    if (flags & FLAG_NONHYP) { c->status = ST_NONHYP; c->status_step = h.accepted; return; }
+    if ((flags & FLAG_NONFINITE) || !(smax <= 1.7976931348623157e308)) {
+        c->status = ST_NONFINITE;
+        c->status_step = h.accepted;
+        return;
+    }
+    const double nu = h.dt * smax;
+    c->nu_last = nu;
+    if (!fixed_dt && nu > cfl_max) {
+        c->rejected = h.rejected + 1;
+        c->retries = h.retries + 1;
+        if (h.retries + 1 > max_retries) { c->status = ST_RETRIES; c->status_step = h.accepted; return; }
+        c->dt = h.dt * cfl_target / nu;
+        return;
+    }
+    c->retries = 0;
+    c->t = h.t + h.dt;
+    c->accepted = h.accepted + 1;
+    c->cur = h.cur + 1 == nbuf ? 0 : h.cur + 1;
+    const long long n = h.nu_count + 1;
+    c->nu_count = n;
+    const double dev = nu - h.nu_mean;
+    const double mean = h.nu_mean + dev / (double)n;
+    c->nu_mean = mean;
+    c->nu_m2 = h.nu_m2 + dev * (nu - mean);
+    if (!fixed_dt && smax > 0.0) c->dt = h.dt * cfl_target / nu;
+}
+
 // Everything a wavefront needs to know about its simulation.
 struct SimDesc {
     int nx, ny, pitch, strips, segs, tile_rows;

@@ -31,47 +31,14 @@ using namespace fvna;
 // Kernels
 // ---------------------------------------------------------------------------
 
-// Accept or reject the attempt just made, from its largest wave speed
-// (CFL control of Sec. 4 opening; rejection rule as stated in include/fvna.h).
-// Runs in its own launch after the step kernel, on one thread per simulation.
-// (Deciding in the step kernel's last wavefront instead needs an agent-scope
-// release fence in every wavefront, which writes back the L2 and cost more
-// than the launch it saves.)
-__device__ void control(const SimDesc& d)
+// Accept or reject the attempt just made (control_attempt of
+// fvna_device.hpp); one thread per simulation, in its own launch after the
+// step kernel.  (Deciding in the step kernel's last wavefront instead needs an
+// agent-scope release fence in every wavefront, which writes back the L2 and
+// cost more than the launch it saves.)
+__device__ __forceinline__ void control(const SimDesc& d)
 {
-    Clock* c = d.clk;
-    // All memory traffic is issued at once, so the launch costs one round
-    // trip: the attempt's largest speed and flags are taken (and cleared for
-    // the next attempt) whether or not the attempt counts -- a step launch
-    // that had nothing to do left them at zero.
-    const unsigned long long sb = atomicExch(&c->smax_bits, 0ull);
-    const unsigned flags = atomicExch(&c->flags, 0u);
-    const Clock h = *c;
-    if (h.status != 0 || h.accepted >= h.target) return;
-    const double smax = __longlong_as_double((long long)sb);
-    c->attempts = h.attempts + 1;
-    if (flags & FLAG_NONHYP) { c->status = ST_NONHYP; c->status_step = h.accepted; return; }
-    if ((flags & FLAG_NONFINITE) || !(smax <= DBL_MAX)) { c->status = ST_NONFINITE; c->status_step = h.accepted; return; }
-    const double nu = h.dt * smax;
-    c->nu_last = nu;
-    if (!d.fixed_dt && nu > d.cfl_max) {
-        c->rejected = h.rejected + 1;
-        c->retries = h.retries + 1;
-        if (h.retries + 1 > d.max_retries) { c->status = ST_RETRIES; c->status_step = h.accepted; return; }
-        c->dt = h.dt * d.cfl_target / nu;
-        return;
-    }
-    c->retries = 0;
-    c->t = h.t + h.dt;
-    c->accepted = h.accepted + 1;
-    c->cur = h.cur ^ 1;
-    const long long n = h.nu_count + 1;
-    c->nu_count = n;
-    const double dev = nu - h.nu_mean;
-    const double mean = h.nu_mean + dev / (double)n;
-    c->nu_mean = mean;
-    c->nu_m2 = h.nu_m2 + dev * (nu - mean);
-    if (!d.fixed_dt && smax > 0.0) c->dt = h.dt * d.cfl_target / nu;
+    control_attempt(d.clk, d.fixed_dt, d.cfl_target, d.cfl_max, d.max_retries, 2);
 }
 
 __global__ void k_ctrl(SimDesc d)

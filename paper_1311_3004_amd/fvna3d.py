@@ -10,7 +10,7 @@ import torch  # noqa: F401  (its HIP runtime first)
 from .fvna import BCS, E_NONFINITE, E_NONHYPERBOLIC, E_RETRIES, PRECISION, FvnaError, fvna_stats
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libfvna3d.so")
+LIB_PATH = os.environ.get("FVNA3D_LIB") or os.path.join(_HERE, "libfvna3d.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it (paper_1311_3004_amd.build3d)")
 lib = ctypes.CDLL(LIB_PATH)
