@@ -201,20 +201,24 @@ fvna_status fvna_sync(fvna_ctx* c);
 
 /* Move the domain ncols cells along +x1 (the moving domain of Sec. 4):
  * afterwards column i holds what column i + ncols held, and the ncols columns
- * that enter on the right hold undisturbed medium (zero perturbation).  The
- * stored values are copied as they are (exact in every precision).  Time, time
- * step and statistics are unchanged; side data stay attached to the domain
- * (the source stays at its left edge), so both x sides must be EXTRAP0,
- * REFLECT or SOURCE.  0 <= ncols <= nx; 0 does nothing.  Asynchronous on the
- * stream; FVNA_E_INVALID for a bad argument. */
+ * that enter on the right hold undisturbed medium (zero perturbation) or, when
+ * side x+ is TAYLOR, the Taylor profile at their path columns at the current
+ * time (the medium ahead of the front).  The kept values are copied as they
+ * are (exact in every precision).  Time, time step and statistics are
+ * unchanged.  The focused source stays at the domain's left edge; Taylor data
+ * (side and ghost values) stay anchored on the path: column i of a domain that
+ * has moved x_off cells lies at path column x_off + i, where the profile of
+ * fvna_set_taylor is evaluated.  The x axis must not be periodic.
+ * 0 <= ncols <= nx; 0 does nothing.  Asynchronous on the stream;
+ * FVNA_E_INVALID for a bad argument. */
 fvna_status fvna_shift(fvna_ctx* c, int32_t ncols);
 
 /* The two stages of Sec. 4 on a moving domain: the domain stays still until
- * the packet centre, travelling at c0, reaches its middle at t1; from then on
- * it follows the packet.  The paper gives no rule for the moves; here the
- * state is checked after every check_every-th accepted step (counted across
- * calls by `phase`), and once t >= t1 the origin moves to
- * quantum * floor((t - t1) c0 / (dx quantum)) cells from the start (fvna_shift
+ * the wave reaches its middle at t1; from then on it follows the wave.  The
+ * paper gives no rule for the moves; here the state is checked after every
+ * check_every-th accepted step (counted across calls by `phase`), and once
+ * t >= t1 the origin moves to quantum * floor((t - t1) speed c0 / (dx quantum))
+ * cells from the start (fvna_shift
  * by the difference; a move of nx cells or more leaves undisturbed medium in
  * the whole domain, and the path offset the recorder uses still advances by
  * the whole move).  The source's second stage (fvna_source .stage2_time,
@@ -223,6 +227,8 @@ typedef struct {
     double t1;                 /* [s], finite */
     int32_t check_every;       /* >= 1 */
     int32_t quantum;           /* cells, >= 1 */
+    double speed;              /* domain speed along x1 in units of c0 (e.g. 1/cos(theta) for
+                                  an oblique front's trace); 0 = 1 */
 } fvna_window;
 typedef struct {
     int64_t x_off;             /* cells the domain has moved (start at 0) */
@@ -280,6 +286,26 @@ fvna_status fvna_get_stats(fvna_ctx* c, fvna_stats* s);
 /* Synchronise and return FP64 sums over the grid of rho', rho u, rho v (SI),
  * computed on the device in a fixed order (identical on every run). */
 fvna_status fvna_sums(fvna_ctx* c, double out[3]);
+
+/* The errors E1 and Einf of eq. (error) (Sec. 4.1) of the current state
+ * against the Taylor profile of fvna_set_taylor, computed on the device in
+ * FP64: over the cells of the straight line along the propagation direction
+ * (cos angle, sin angle) of length 2 half_length_m centred on the analytic
+ * front at the current time t, whose point at t = 0 is (front0_x_m,
+ * front0_y_m) (so the front is at that point + c0 t (cos, sin)),
+ *   E1 = sum |R - R_ref| / sum |R_ref|,  Einf = max |R - R_ref| / max |R_ref|,
+ * with R = rho'/rho0 and R_ref = -a tanh((xi - c0 t)/w) at the cell centres.
+ * The line takes one cell per column when |cos| >= |sin| (columns i with
+ * (i + 1/2) dx within half_length_m cos of the front, the cell of row
+ * floor(y(i)/dx) the line crosses there), else one cell per row; cells
+ * outside the domain are skipped.  Coordinates are path coordinates: on a
+ * moving domain column i lies at path column x_off + i.  The sums run in a
+ * fixed order (the same result on every run).  Synchronises the stream (steps
+ * owed are taken first).  out[0] = E1, out[1] = Einf.  FVNA_E_INVALID without
+ * Taylor data, for a non-positive half length or when no cell of the line is
+ * in the domain. */
+fvna_status fvna_taylor_errors(fvna_ctx* c, double front0_x_m, double front0_y_m, double half_length_m,
+                               double out[2]);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, serving loops, harnesses that forbid hipMalloc): the sums of

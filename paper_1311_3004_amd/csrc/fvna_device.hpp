@@ -452,11 +452,18 @@ __device__ __forceinline__ void geometric_half_step(Cell<T>& q, T hr)
 // Analytic boundary data (always evaluated in FP64).
 // ---------------------------------------------------------------------------
 
-// Taylor shock-like profile, eq. OurTaylorS with the rotation of Sec. 4.1.
-__device__ __forceinline__ void taylor_at(const SimDesc& d, double x, double y, double t,
+// Taylor shock-like profile, eq. OurTaylorS with the rotation of Sec. 4.1,
+// at domain coordinates (x, y).  The profile is anchored on the path of a
+// moving domain: x0 = ta_x0 - x_off, the profile's origin seen from a domain
+// that has moved x_off cells (taylor_x0).
+__device__ __forceinline__ double taylor_x0(const SimDesc& d, long long x_off)
+{
+    return d.ta_x0 - (double)x_off;
+}
+__device__ __forceinline__ void taylor_at(const SimDesc& d, double x0, double x, double y, double t,
                                           double& R, double& M, double& N)
 {
-    const double xi = (x - d.ta_x0) * d.ta_cos + (y - d.ta_y0) * d.ta_sin;
+    const double xi = (x - x0) * d.ta_cos + (y - d.ta_y0) * d.ta_sin;
     R = -d.ta_amp * tanh((xi - t) / d.ta_w);
     M = R * d.ta_cos;
     N = R * d.ta_sin;
@@ -667,6 +674,7 @@ __device__ __forceinline__ void march(const SimDesc& d, int strip, int seg)
     seg_bounds(d, seg, r0, r1);
     const Clock* clk = d.clk;
     const double tn = clk->t;
+    const double tx0 = taylor_x0(d, clk->x_off);
     const T dt = (T)clk->dt;
     const int cur = clk->cur;
     const long long plane = d.plane;
@@ -761,7 +769,7 @@ __device__ __forceinline__ void march(const SimDesc& d, int strip, int seg)
             q.M *= msign;
             if (xkind == 1) {
                 double R, M, N;
-                taylor_at(d, col + 0.5, vr + 0.5, tn, R, M, N);
+                taylor_at(d, tx0, col + 0.5, vr + 0.5, tn, R, M, N);
                 q.R = (T)R; q.M = (T)M; q.N = (T)N;
             } else if (xkind == 2) {
                 const bool row_ok = !GHOST || (unsigned)vr < (unsigned)ny;
@@ -808,14 +816,14 @@ __device__ __forceinline__ void march(const SimDesc& d, int strip, int seg)
     // that went through the same first fractional step as the interior
     auto xsweep_taylor_ghost = [&](int vr) -> Cell<T> {
         double R, M, N;
-        taylor_at(d, scol + 0.5, vr + 0.5, tn, R, M, N);
+        taylor_at(d, tx0, scol + 0.5, vr + 0.5, tn, R, M, N);
         return xsweep_core(Flag<true>{}, vr, Cell<T>{(T)R, (T)M, (T)N});
     };
 
     // analytic (Taylor) velocities of a ghost cell
     auto taylor_uv = [&](double x, double y, T& uu, T& vv) {
         double R, M, N;
-        taylor_at(d, x, y, tn, R, M, N);
+        taylor_at(d, tx0, x, y, tn, R, M, N);
         uu = (T)(M / (1.0 + R));
         vv = (T)(N / (1.0 + R));
     };

@@ -81,7 +81,7 @@ __device__ Cell<T> cell_at(const SimDesc& d, int i, int j, double t)
         const int b = d.bc[side];
         if (b == BC_TAYLOR) {
             double R, M, N;
-            taylor_at(d, i + 0.5, j + 0.5, t, R, M, N);
+            taylor_at(d, taylor_x0(d, d.clk->x_off), i + 0.5, j + 0.5, t, R, M, N);
             return Cell<T>{(T)R, (T)M, (T)N};
         }
         if (b == BC_SOURCE) {
@@ -232,26 +232,38 @@ __global__ void k_export(SimDesc d, double* __restrict__ dst, int field, int row
 }
 
 // Moving domain (Sec. 4): the current state moved `ncols` cells along +x1 into
-// the other buffer, undisturbed medium (stored zero, whatever the scale)
-// entering on the right and in the row padding.  Raw copies of the stored
+// the other buffer.  Entering on the right: undisturbed medium (stored zero,
+// whatever the scale), or, when side x+ holds Taylor data, the profile at the
+// new path columns at the time of the move (the medium ahead of the front);
+// the row padding stays zero.  Kept columns are raw copies of the stored
 // values: no conversion, so a move is exact in every precision.  k_flip then
 // makes the moved state current; it runs after every block of k_shift has
-// read `cur`.
-template <typename S>
+// read `cur` and x_off.
+template <typename S, typename T>
 __global__ __launch_bounds__(256) void k_shift(SimDesc d, int ncols)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= d.pitch) return;
-    const int cur = d.clk->cur;
+    const Clock* clk = d.clk;
+    const int cur = clk->cur;
     const S* __restrict__ src = (const S*)d.buf[cur];
     S* __restrict__ dst = (S*)d.buf[cur ^ 1];
     const bool inside = i < d.nx - ncols;
+    const bool fill = !inside && i < d.nx && d.bc[1] == BC_TAYLOR;
+    const double x0 = taylor_x0(d, clk->x_off + ncols), t = clk->t;
     for (int r = blockIdx.y; r < 3 * d.ny; r += gridDim.y) {
         const int field = r / d.ny, row = r - field * d.ny;
         const size_t base = (size_t)field * d.plane + (size_t)row * d.pitch;
         S v;
-        if (inside) v = src[base + i + ncols];
-        else __builtin_memset(&v, 0, sizeof(S));
+        if (inside) {
+            v = src[base + i + ncols];
+        } else if (fill) {
+            double q[3];
+            taylor_at(d, x0, i + 0.5, row + 0.5, t, q[0], q[1], q[2]);
+            v = Codec<S, T>::st((T)q[field], d.inv_scale[field]);
+        } else {
+            __builtin_memset(&v, 0, sizeof(S));
+        }
         dst[base + i] = v;
     }
 }
@@ -344,6 +356,68 @@ __global__ __launch_bounds__(256) void k_sums_final(const double* __restrict__ p
         out[0] = sh[0][0] * f0;
         out[1] = sh[1][0] * f1;
         out[2] = sh[2][0] * f2;
+    }
+}
+
+// Errors of eq. (error) on a line of cells (fvna_taylor_errors): one block of
+// 256 threads, thread k takes line cells k, k + 256, ...; a fixed tree
+// reduces the four FP64 accumulators (sum |R - R_ref|, sum |R_ref|, and the
+// two maxima).  Line geometry in SI metres, as the host describes it: cells
+// a0 .. a0 + n - 1 along the line's main axis (columns, or rows when steep),
+// the other index the floor of the line's coordinate there.
+struct ErrLine {
+    double fx, fy;       // front point at time t [m]
+    double c, s;         // propagation direction
+    double dx, x0;       // mesh spacing, Taylor origin on the path [m]
+    double c0t, w, amp;  // c0 t [m], tanh width [m], amplitude (dimensionless)
+    long long a0, n, x_off;
+    int steep;
+};
+
+template <typename S, typename T>
+__global__ __launch_bounds__(256) void k_taylor_err(SimDesc d, ErrLine L, double* __restrict__ out)
+{
+    __shared__ double sh[4][256];
+    double se = 0.0, sr = 0.0, me = 0.0, mr = 0.0;
+    const S* R = (const S*)d.buf[d.clk->cur];
+    for (long long k = threadIdx.x; k < L.n; k += 256) {
+        const long long a = L.a0 + k;
+        long long ip, jp;
+        if (!L.steep) {
+            ip = a;
+            jp = (long long)floor((L.fy + (((double)a + 0.5) * L.dx - L.fx) * L.s / L.c) / L.dx);
+        } else {
+            jp = a;
+            ip = (long long)floor((L.fx + (((double)a + 0.5) * L.dx - L.fy) * L.c / L.s) / L.dx);
+        }
+        const long long i = ip - L.x_off;
+        if (i < 0 || i >= d.nx || jp < 0 || jp >= d.ny) continue;
+        const double xi = (((double)ip + 0.5) * L.dx - L.x0) * L.c + ((double)jp + 0.5) * L.dx * L.s;
+        const double ref = -L.amp * tanh((xi - L.c0t) / L.w);
+        const double v = (double)Codec<S, T>::ld(R[(size_t)jp * (size_t)d.pitch + (size_t)i], d.scale[0]);
+        const double e = fabs(v - ref);
+        se += e;
+        sr += fabs(ref);
+        me = fmax(me, e);
+        mr = fmax(mr, fabs(ref));
+    }
+    sh[0][threadIdx.x] = se;
+    sh[1][threadIdx.x] = sr;
+    sh[2][threadIdx.x] = me;
+    sh[3][threadIdx.x] = mr;
+    __syncthreads();
+    for (int h = 128; h >= 1; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + h];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + h];
+            sh[2][threadIdx.x] = fmax(sh[2][threadIdx.x], sh[2][threadIdx.x + h]);
+            sh[3][threadIdx.x] = fmax(sh[3][threadIdx.x], sh[3][threadIdx.x + h]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = sh[0][0] / sh[1][0];
+        out[1] = sh[2][0] / sh[3][0];
     }
 }
 
@@ -531,6 +605,7 @@ struct Launcher {
     void (*sums)(const SimDesc&, const void* state, double* part, double* out, const double* factor, hipStream_t);
     void (*shift)(const SimDesc&, int, hipStream_t);
     void (*record)(const SimDesc&, const RecDesc&, hipStream_t);
+    void (*taylor_err)(const SimDesc&, const ErrLine&, double*, hipStream_t);
 };
 
 template <typename S, typename T, int AXI>
@@ -566,11 +641,14 @@ Launcher make_launcher()
     };
     L.shift = [](const SimDesc& d, int ncols, hipStream_t s) {
         const int rows = std::min(3 * d.ny, 65535);
-        hipLaunchKernelGGL(k_shift<S>, dim3((d.pitch + 255) / 256, rows), dim3(256), 0, s, d, ncols);
+        hipLaunchKernelGGL((k_shift<S, T>), dim3((d.pitch + 255) / 256, rows), dim3(256), 0, s, d, ncols);
         hipLaunchKernelGGL(k_flip, dim3(1), dim3(64), 0, s, d.clk, ncols);
     };
     L.record = [](const SimDesc& d, const RecDesc& r, hipStream_t s) {
         hipLaunchKernelGGL((k_record<S, T>), dim3((d.nx + 255) / 256), dim3(256), 0, s, d, r);
+    };
+    L.taylor_err = [](const SimDesc& d, const ErrLine& e, double* out, hipStream_t s) {
+        hipLaunchKernelGGL((k_taylor_err<S, T>), dim3(1), dim3(256), 0, s, d, e, out);
     };
     return L;
 }
@@ -629,6 +707,8 @@ struct fvna_ctx {
     int device = 0;
     bool recording = false;     // a recorder follows every attempt
     RecDesc rec{};
+    bool taylor = false;        // fvna_set_taylor was called
+    double ta_amp_pa = 0.0, ta_x0_m = 0.0;
 };
 
 // One attempt on stream s: the step, the CFL decision, the recorder if any.
@@ -840,6 +920,9 @@ fvna_status fvna_set_taylor(fvna_ctx* c, double amplitude_pa, double x0_m, doubl
     c->d.ta_y0 = 0.0;
     c->d.ta_cos = std::cos(angle);
     c->d.ta_sin = std::sin(angle);
+    c->taylor = true;
+    c->ta_amp_pa = amplitude_pa;
+    c->ta_x0_m = x0_m;
     drop_graph(c);
     return FVNA_OK;
 }
@@ -951,11 +1034,8 @@ fvna_status fvna_shift(fvna_ctx* c, int32_t ncols)
 {
     if (!c) return fail(FVNA_E_INVALID, "ctx is NULL");
     if (ncols < 0 || ncols > c->p.nx) return fail(FVNA_E_INVALID, "ncols must be in [0, nx]");
-    for (int side = 0; side < 2; ++side) {
-        const int b = c->p.bc[side];
-        if (b == FVNA_BC_PERIODIC || b == FVNA_BC_TAYLOR)
-            return fail(FVNA_E_INVALID, "moving the domain needs EXTRAP0, REFLECT or SOURCE x sides");
-    }
+    if (c->p.bc[0] == FVNA_BC_PERIODIC)
+        return fail(FVNA_E_INVALID, "a periodic x axis cannot move");
     if (ncols == 0) return FVNA_OK;
     c->L.shift(c->d, ncols, c->stream);
     HIP_TRY(hipGetLastError());
@@ -968,15 +1048,13 @@ fvna_status fvna_step_window(fvna_ctx* c, const fvna_window* w, fvna_window_stat
     if (nsteps < 0) return fail(FVNA_E_INVALID, "nsteps must be >= 0");
     if (w->check_every < 1 || w->quantum < 1 || !std::isfinite(w->t1))
         return fail(FVNA_E_INVALID, "need check_every >= 1, quantum >= 1 and a finite t1");
+    if (!(w->speed >= 0.0) || !std::isfinite(w->speed)) return fail(FVNA_E_INVALID, "speed must be finite and >= 0");
     if (st->x_off < 0 || st->phase < 0 || st->phase >= w->check_every)
         return fail(FVNA_E_INVALID, "window state out of range");
-    for (int side = 0; side < 2; ++side) {
-        const int b = c->p.bc[side];
-        if (b == FVNA_BC_PERIODIC || b == FVNA_BC_TAYLOR)
-            return fail(FVNA_E_INVALID, "moving the domain needs EXTRAP0, REFLECT or SOURCE x sides");
-    }
+    if (c->p.bc[0] == FVNA_BC_PERIODIC) return fail(FVNA_E_INVALID, "a periodic x axis cannot move");
     const fvna_params& p = c->p;
     const double t1 = w->t1 * p.c0 / p.dx;        // cells travelled at c0 per unit time
+    const double speed = w->speed > 0.0 ? w->speed : 1.0;
     while (nsteps > 0) {
         const int64_t k = std::min<int64_t>(nsteps, w->check_every - st->phase);
         fvna_status s = fvna_step(c, k);
@@ -991,7 +1069,7 @@ fvna_status fvna_step_window(fvna_ctx* c, const fvna_window* w, fvna_window_stat
         s = read_clock(c, &h);
         if (s) return s;
         if (!(h.t >= t1)) continue;
-        const int64_t target = (int64_t)w->quantum * (int64_t)std::floor((h.t - t1) / w->quantum);
+        const int64_t target = (int64_t)w->quantum * (int64_t)std::floor((h.t - t1) * speed / w->quantum);
         if (target <= st->x_off) continue;
         // a move of nx or more columns leaves undisturbed medium everywhere;
         // the device offset still advances by the whole move, so that path
@@ -1122,6 +1200,49 @@ fvna_status fvna_sums(fvna_ctx* c, double out[3])
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(c->stream));
     HIP_TRY(hipMemcpy(out, res, 3 * sizeof(double), hipMemcpyDeviceToHost));
+    return FVNA_OK;
+}
+
+fvna_status fvna_taylor_errors(fvna_ctx* c, double front0_x_m, double front0_y_m, double half_length_m,
+                               double out[2])
+{
+    if (!c || !out) return fail(FVNA_E_INVALID, "NULL argument");
+    if (!c->taylor) return fail(FVNA_E_INVALID, "no Taylor profile set (fvna_set_taylor)");
+    if (!(half_length_m > 0.0) || !std::isfinite(front0_x_m) || !std::isfinite(front0_y_m))
+        return fail(FVNA_E_INVALID, "need a positive half length and a finite front point");
+    fvna_status s = fvna_sync(c);
+    if (s != FVNA_OK && !is_device_error(s)) return s;
+    Clock h;
+    s = read_clock(c, &h);
+    if (s) return s;
+    const fvna_params& p = c->p;
+    ErrLine L;
+    L.c = c->d.ta_cos;
+    L.s = c->d.ta_sin;
+    L.dx = p.dx;
+    L.x0 = c->ta_x0_m;
+    const double t = h.t * (p.dx / p.c0);
+    L.c0t = p.c0 * t;
+    L.fx = front0_x_m + L.c0t * L.c;
+    L.fy = front0_y_m + L.c0t * L.s;
+    L.w = c->d.ta_w * p.dx;
+    L.amp = c->d.ta_amp;
+    L.x_off = h.x_off;
+    L.steep = std::fabs(L.c) < std::fabs(L.s) ? 1 : 0;
+    const double f = L.steep ? L.fy : L.fx, cs = L.steep ? L.s : L.c;
+    const double lo = std::ceil((f - half_length_m * cs) / p.dx - 0.5);
+    const double hi = std::floor((f + half_length_m * cs) / p.dx - 0.5);
+    if (!(hi >= lo) || !(std::fabs(hi) < 4.0e18) || !(std::fabs(lo) < 4.0e18))
+        return fail(FVNA_E_INVALID, "the line has no cells");
+    L.a0 = (long long)lo;
+    L.n = (long long)hi - (long long)lo + 1;
+    double* res = (double*)(c->scratch + OFF_SUMOUT);
+    c->L.taylor_err(c->d, L, res, c->stream);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipMemcpy(out, res, 2 * sizeof(double), hipMemcpyDeviceToHost));
+    if (!std::isfinite(out[0]) || !std::isfinite(out[1]))
+        return fail(FVNA_E_INVALID, "no cell of the line lies in the domain");
     return FVNA_OK;
 }
 

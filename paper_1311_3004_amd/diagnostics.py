@@ -139,12 +139,15 @@ def spectrum(t, p, freq, n=8, packet_cycles=4.0):
     return np.array([abs(2.0 / D * np.sum(w * p * np.exp(-2j * np.pi * k * freq * t)))
                      for k in range(1, n + 1)])
 
-def line_cells(w, t, half_length=5.0):
+def line_cells(w, t, half_length=5.0, x_off=0, nx=None):
     """Cells on the line along the propagation direction of the oblique
     Taylor workload, half_length L on each side of the analytic front at time
     t: one cell per column (per row when the line is steeper than 45 degrees),
-    the cell containing the line's point there.  Returns (i, j) index arrays."""
-    c, s = np.cos(w["theta"]), np.sin(w["theta"])
+    the cell containing the line's point there.  Returns (i, j) path index
+    arrays; on a domain that has moved x_off cells (nx columns wide) only the
+    cells inside it are kept.  The direction cosines come from the C library's
+    cos and sin, as the GPU library's (math.cos, not numpy's vector code)."""
+    c, s = math.cos(w["theta"]), math.sin(w["theta"])
     dx, L = w["dx"], w["unit_m"]
     c0 = w["medium"]["c0"]
     fx = w["front0_m"][0] + c0 * t * c
@@ -159,22 +162,23 @@ def line_cells(w, t, half_length=5.0):
                       int(np.floor((fy + half_length * L * s) / dx - 0.5)) + 1)
         x = fx + ((j + 0.5) * dx - fy) * c / s
         i = np.floor(x / dx).astype(int)
-    keep = (i >= 0) & (i < w["nx"]) & (j >= 0) & (j < w["ny"])
+    nx = w["nx"] if nx is None else nx
+    keep = (i - x_off >= 0) & (i - x_off < nx) & (j >= 0) & (j < w["ny"])
     return i[keep], j[keep]
 
 
-def taylor_errors(w, t, R):
+def taylor_errors(w, t, R, x_off=0):
     """E1 and Einf of eq. (error) for the oblique Taylor workload: the
     dimensionless perturbation R = rho'/rho0 on the cells of line_cells,
     against -a tanh((xi - c0 t)/w) at their centres, relative to the
-    reference's own norms.  R is the [ny][nx] field (or a window whose origin
-    is given by the caller's index shift)."""
-    i, j = line_cells(w, t)
-    c, s = np.cos(w["theta"]), np.sin(w["theta"])
+    reference's own norms.  R is the [ny][nx] field of a domain that has
+    moved x_off cells (0: fixed); the line is in path coordinates."""
+    i, j = line_cells(w, t, x_off=x_off, nx=R.shape[1])
+    c, s = math.cos(w["theta"]), math.sin(w["theta"])
     dx = w["dx"]
     xi = ((i + 0.5) * dx - w["taylor"]["x0_m"]) * c + (j + 0.5) * dx * s
     ref = -w["amplitude"] * np.tanh((xi - w["medium"]["c0"] * t) / w["tanh_unit_m"])
-    num = R[j, i]
+    num = R[j, i - x_off]
     d = np.abs(num - ref)
     return float(np.sum(d) / np.sum(np.abs(ref))), float(np.max(d) / np.max(np.abs(ref)))
 

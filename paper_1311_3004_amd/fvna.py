@@ -33,7 +33,7 @@ EXPORTS = [
     "fvna_set_state", "fvna_set_clock", "fvna_step", "fvna_sync", "fvna_shift", "fvna_step_window",
     "fvna_set_recorder",
     "fvna_get_state", "fvna_get_window",
-    "fvna_get_stats", "fvna_sums", "fvna_sums_noalloc", "fvna_time_step_kernel", "fvna_autotune", "fvna_get_tile_rows",
+    "fvna_get_stats", "fvna_sums", "fvna_sums_noalloc", "fvna_taylor_errors", "fvna_time_step_kernel", "fvna_autotune", "fvna_get_tile_rows",
     "fvna_last_error", "fvna_destroy", "fvna_batch_create", "fvna_batch_set_state",
     "fvna_batch_step", "fvna_batch_sync", "fvna_batch_get_state", "fvna_batch_get_stats",
     "fvna_batch_time_step_kernel", "fvna_batch_destroy",
@@ -63,7 +63,8 @@ ENVELOPES = {"ramp": 0, "packet": 1}
 
 
 class fvna_window(ctypes.Structure):
-    _fields_ = [("t1", ctypes.c_double), ("check_every", ctypes.c_int32), ("quantum", ctypes.c_int32)]
+    _fields_ = [("t1", ctypes.c_double), ("check_every", ctypes.c_int32), ("quantum", ctypes.c_int32),
+                ("speed", ctypes.c_double)]
 
 
 class fvna_window_state(ctypes.Structure):
@@ -114,6 +115,7 @@ def _load():
         "fvna_get_stats": (st, [vp, P(fvna_stats)]),
         "fvna_sums": (st, [vp, dp]),
         "fvna_sums_noalloc": (st, [P(fvna_params), vp, vp, vp]),
+        "fvna_taylor_errors": (st, [vp, d, d, d, dp]),
         "fvna_time_step_kernel": (st, [vp, i32, dp]),
         "fvna_autotune": (st, [vp, P(i32)]),
         "fvna_get_tile_rows": (st, [vp, P(i32)]),
@@ -294,6 +296,14 @@ class Sim:
         out = np.zeros(3)
         check(lib.fvna_sums(self.handle, _dptr(out)))
         return out
+
+    def fvna_taylor_errors(self, front0_x_m, front0_y_m, half_length_m):
+        """(E1, Einf) of eq. (error) on the line along the Taylor profile's
+        propagation direction centred on its analytic front (device, FP64)."""
+        out = np.zeros(2)
+        check(lib.fvna_taylor_errors(self.handle, float(front0_x_m), float(front0_y_m), float(half_length_m),
+                                     _dptr(out)))
+        return float(out[0]), float(out[1])
 
     def fvna_time_step_kernel(self, reps):
         ms = ctypes.c_double()

@@ -1,0 +1,109 @@
+"""The Taylor-shock study of Sec. 4.1 on the GPU path: the FP64 error norms
+of eq. (error) computed on the device against the host's, and an oblique
+front on the two-stage moving domain of Sec. 4 (analytic data on all four
+sides, anchored on the path) against the oracle's moving domain."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("theta", [0.0, math.pi / 8, math.pi / 4, 3 * math.pi / 8])
+def test_taylor_errors_on_device_match_host(theta):
+    """fvna_taylor_errors (device, FP64, fixed order) against
+    diagnostics.taylor_errors (numpy) on the exported state: the same line
+    cells, the same reference.  The two differ only by rounding: the device's
+    and the C library's tanh may differ in the last bit, and the export
+    rounds R through rho0, a few 1e-23 on errors of 1e-9 and more."""
+    from paper_1311_3004_amd import diagnostics as dg, fvna, inputs
+    w = inputs.taylor_oblique(10, theta, precision="f64")
+    _say(f"case: taylor errors theta={theta:.4f} {w['nx']}x{w['ny']}")
+    s = fvna.sim_from_workload(w, precision="f64")
+    s.fvna_step(150)
+    st = s.fvna_get_stats()
+    hl = 5.0 * w["unit_m"]
+    e1, einf = s.fvna_taylor_errors(w["front0_m"][0], w["front0_m"][1], hl)
+    rp, _, _ = s.fvna_get_state()
+    h1, hinf = dg.taylor_errors(w, st["t"], rp / w["medium"]["rho0"])
+    _say(f"  device E1 {e1:.6e} Einf {einf:.6e}; host {h1:.6e} {hinf:.6e}")
+    assert 1e-6 < h1 < 1.0 and 1e-6 < hinf < 2.0
+    assert abs(e1 - h1) <= 1e-12 * h1
+    assert abs(einf - hinf) <= 1e-12 * hinf
+    with pytest.raises(fvna.FvnaError):
+        s.fvna_taylor_errors(w["front0_m"][0], w["front0_m"][1], -1.0)
+    with pytest.raises(fvna.FvnaError):          # the line far outside the domain
+        s.fvna_taylor_errors(1e3, 1e3, hl)
+    s.fvna_destroy()
+
+
+def _moving_setup(precision):
+    """The oracle pin's oblique front (theta_T = pi/8, amplitude 1e-3, tanh
+    width 1.5 cells) in SI units for the library: 96 x 24 cells, Taylor data
+    on all four sides, the domain still until the front's trace on the middle
+    row reaches the middle column, then moving at the trace speed c0/cos in
+    jumps of 4 cells, checked every 5 steps."""
+    th = math.pi / 8
+    c, s = math.cos(th), math.sin(th)
+    amp, width, beta = 1e-3, 1.5, 3.5
+    med = {"c0": 1500.0, "rho0": 1000.0, "beta": beta}
+    dx = 1e-4
+    med["delta"] = beta * amp * width * med["c0"] * dx        # delta~ = beta a w (travelling balance)
+    ny, nx = 24, 96
+    x0 = 24.0
+    t1 = (nx / 2 - (x0 - (ny / 2) * s / c)) * c               # dimensionless (dx / c0)
+    return th, c, amp, width, med, dx, ny, nx, x0, t1
+
+
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-10), ("f32", 2e-6)])
+def test_moving_domain_taylor_vs_oracle(precision, tol):
+    """fvna_step_window with Taylor sides (entering columns filled with the
+    profile at their path columns, side data at path coordinates) against the
+    oracle's run_window on the same set-up: the whole window and its offset
+    after 90 adaptive steps (14 moves), then the error norms of the moved
+    state on the device against the host's in path coordinates."""
+    import oracle
+    from paper_1311_3004_amd import diagnostics as dg, fvna
+    th, c, amp, width, med, dx, ny, nx, x0, t1 = _moving_setup(precision)
+    p0 = med["rho0"] * med["c0"] ** 2
+    tay_si = {"amplitude_pa": amp * p0, "x0_m": x0 * dx, "angle": th}
+    po = oracle.make_params_si(nx, ny, dx, med["c0"], med["rho0"], med["beta"], med["delta"],
+                               bc=("taylor",) * 4, taylor_si=tay_si)
+    q = np.array([[oracle.taylor_value(po, i + 0.5, j + 0.5, 0.0) for i in range(nx)] for j in range(ny)])
+    R0, M0, N0 = q[..., 0], q[..., 1], q[..., 2]
+    steps = 90
+    _say(f"case: moving Taylor domain {precision} {nx}x{ny}, {steps} steps")
+    Ro, Mo, No, info, xo = oracle.run_window(po, R0, M0, N0, steps, 0.0, 0.0, t1, 5, 4, speed=1.0 / c)
+    assert info["status"] == 0 and xo >= 40
+    p = fvna.make_params(nx, ny, dx, med, bc=("taylor",) * 4, precision=precision)
+    sim = fvna.Sim(p)
+    sim.fvna_set_taylor(tay_si["amplitude_pa"], tay_si["x0_m"], th)
+    rc = med["rho0"] * med["c0"]
+    sim.fvna_set_state(R0 * med["rho0"], M0 * rc, N0 * rc)
+    win = fvna.fvna_window(t1 * dx / med["c0"], 5, 4, 1.0 / c)
+    ws = fvna.fvna_window_state(0, 0)
+    sim.fvna_step_window(win, ws, steps)
+    st = sim.fvna_get_stats()
+    rp, mx, my = sim.fvna_get_state()
+    g = (rp / med["rho0"], mx / rc, my / rc)
+    assert st["steps"] == steps and ws.x_off == xo
+    assert abs(st["t"] * med["c0"] / dx - info["t"]) <= 1e-9 * info["t"]
+    err = max(np.max(np.abs(a - b)) for a, b in zip(g, (Ro, Mo, No))) / amp
+    _say(f"  x_off {ws.x_off}, max |diff| / a = {err:.3e}")
+    assert err <= tol
+    if precision == "f64":
+        # error norms on the moved domain: the line in path coordinates
+        wl = {"theta": th, "dx": dx, "unit_m": 5.0 * dx, "medium": med, "front0_m": (x0 * dx, 0.0),
+              "nx": nx, "ny": ny, "taylor": {"x0_m": x0 * dx}, "amplitude": amp, "tanh_unit_m": width * dx}
+        e1, einf = sim.fvna_taylor_errors(x0 * dx, 0.0, 5.0 * wl["unit_m"])
+        h1, hinf = dg.taylor_errors(wl, st["t"], g[0], x_off=int(ws.x_off))
+        _say(f"  moved-domain errors: device {e1:.6e} {einf:.6e}, host {h1:.6e} {hinf:.6e}")
+        assert abs(e1 - h1) <= 1e-12 * h1 and abs(einf - hinf) <= 1e-12 * hinf
+    sim.fvna_destroy()
