@@ -320,3 +320,37 @@ def run_window(p, R, M, N, nsteps, t, dt, t1, check_every, quantum, x_off=0, spe
                 R, M, N = shift(R, M, N, target - x_off, fill)
                 x_off = target
     return R, M, N, info, x_off
+
+
+def taylor_line_errors(p, t, R, front0, half_length, x_off=0):
+    """E1 and Einf of eq. (error) (Sec. 4.1) of the dimensionless density
+    perturbation R ([ny][nx] of a domain that has moved x_off cells) against
+    the Taylor profile of p (taylor_value, p's taylor_x0 on the path) at time
+    t: over the cells of the straight line of length 2 half_length along the
+    propagation direction, centred on the analytic front front0 + t (cos, sin)
+    (reading R9: one cell per column, the cell the line crosses there; one per
+    row when the line is steeper than 45 degrees), E1 = sum |R - R_ref| /
+    sum |R_ref|, Einf = max |R - R_ref| / max |R_ref|.  Lengths in cells, time
+    in dx/c0.  Plain loops, test infrastructure only."""
+    import math
+    c, s = math.cos(p.taylor_angle), math.sin(p.taylor_angle)
+    fx, fy = front0[0] + t * c, front0[1] + t * s
+    ny, nx = R.shape
+    cells = []
+    if abs(c) >= abs(s):
+        for i in range(math.ceil(fx - half_length * c - 0.5), math.floor(fx + half_length * c - 0.5) + 1):
+            cells.append((i, math.floor(fy + (i + 0.5 - fx) * s / c)))
+    else:
+        for j in range(math.ceil(fy - half_length * s - 0.5), math.floor(fy + half_length * s - 0.5) + 1):
+            cells.append((math.floor(fx + (j + 0.5 - fy) * c / s), j))
+    num = den = big = bigref = 0.0
+    for i, j in cells:
+        if not (0 <= i - x_off < nx and 0 <= j < ny):
+            continue
+        ref = taylor_value(p, i + 0.5, j + 0.5, t)[0]
+        e = abs(R[j, i - x_off] - ref)
+        num += e
+        den += abs(ref)
+        big = max(big, e)
+        bigref = max(bigref, abs(ref))
+    return num / den, big / bigref

@@ -132,6 +132,24 @@ def taylor_oblique(eta, theta, cfl_target=0.9, reading="rise", amplitude=1e-7, t
             "state": (rp, mom * c, mom * s)}
 
 
+def taylor_oblique_window(w, width_l=24.0):
+    """The oblique Taylor workload `w` (taylor_oblique) cut to a mobile domain
+    width_l units L wide (path columns 0 .. nx_w - 1 at the start, the fixed
+    run's height) and its window rule: t1 [s] when the front point
+    front0 + c0 t (cos, sin) reaches the middle column, domain speed
+    cos(theta) in units of c0 (the front point's speed along x1, which keeps
+    the error line centred), moves in quarter-unit jumps checked every 4
+    steps.  Returns (workload, window)."""
+    eta = w["eta"]
+    nxw = int(np.ceil(width_l * eta))
+    rp, mx, my = w["state"]
+    ww = dict(w, nx=nxw, state=(rp[:, :nxw].copy(), mx[:, :nxw].copy(), my[:, :nxw].copy()))
+    c = float(np.cos(w["theta"]))
+    t1 = (0.5 * nxw * w["dx"] - w["front0_m"][0]) / (w["medium"]["c0"] * c)
+    window = {"t1": t1, "check_every": 4, "quantum": max(1, int(round(eta / 4))), "speed": c}
+    return ww, window
+
+
 def c2_pulse_fp32(nx=4096, ny=4096, seed=2):
     """FP32 Cartesian 4096^2: 2 MPa Gaussian (sigma 20 cells) at a seed-chosen
     centre in [1536, 2560)^2 plus 0.5% white noise, absorbing (zero-order

@@ -8,6 +8,15 @@ log E against log eta over eta = 5 ... 82, with their R^2.
     python -m paper_1311_3004_amd.taylor_report              # all 125 runs, reading "rise"
     python -m paper_1311_3004_amd.taylor_report all tanh      # the other reading of the unit
     python -m paper_1311_3004_amd.taylor_report 0.3927,41,0.9 rise f32   # one run
+    python -m paper_1311_3004_amd.taylor_report all rise f64 window      # on the mobile domain
+
+The mobile domain of Sec. 4 (last argument "window"): WINDOW_L units wide
+with the fixed run's height, Taylor data on all four sides in both stages
+(anchored on the path), still until the front point -- the point of the
+front on the error line's axis -- reaches the middle column, then moving
+along x1 at that point's speed c0 cos(theta_T) in quarter-unit jumps, so
+that the error line stays centred in the window.  The errors are computed
+on the device (fvna_taylor_errors) in path coordinates.
 
 One JSON line per run, then one summary line per (theta_T, norm) with the
 statistics Table 1 prints: best / worst / mean rate over nu_W, worst R^2,
@@ -29,31 +38,43 @@ ETAS = (5, 10, 20, 41, 82)
 NUS = (0.6, 0.7, 0.8, 0.9, 0.99)
 
 
-def run(theta, eta, nu, reading="rise", precision="f64"):
+WINDOW_L = 24.0           # width of the mobile domain in units L
+
+
+def run(theta, eta, nu, reading="rise", precision="f64", mobile=False):
     w = inputs.taylor_oblique(eta, theta, cfl_target=nu, reading=reading, precision=precision)
+    window = None
+    if mobile:
+        w, window = inputs.taylor_oblique_window(w, WINDOW_L)
     t_wall = time.time()
     s = fvna.sim_from_workload(w, precision=precision)
     t_end = w["t_end"]
+    if window is not None:
+        win = fvna.fvna_window(window["t1"], window["check_every"], window["quantum"], window["speed"])
+        ws = fvna.fvna_window_state(0, 0)
     while True:
         st = s.fvna_get_stats()
         if st["t"] >= t_end or st["status"] != 0:
             break
         left = (t_end - st["t"]) / st["dt_next"]
-        s.fvna_step(max(1, int(left) - 2) if left > 4 else 1)
+        n = max(1, int(left) - 2) if left > 4 else 1
+        if window is None:
+            s.fvna_step(n)
+        else:
+            s.fvna_step_window(win, ws, n)
     st = s.fvna_get_stats()
-    i, j = dg.line_cells(w, st["t"])
-    i0, j0 = int(i.min()), int(j.min())
-    rp, _, _ = s.fvna_get_window(i0, j0, int(i.max()) - i0 + 1, int(j.max()) - j0 + 1)
+    e1, einf = s.fvna_taylor_errors(w["front0_m"][0], w["front0_m"][1], 5.0 * w["unit_m"])
     s.fvna_destroy()
-    R = np.zeros((w["ny"], w["nx"]))
-    R[j0:j0 + rp.shape[0], i0:i0 + rp.shape[1]] = rp / w["medium"]["rho0"]
-    e1, einf = dg.taylor_errors(w, st["t"], R)
     wall = time.time() - t_wall
-    return {"theta": theta, "eta": eta, "nu_W": nu, "reading": reading, "precision": precision,
-            "nx": w["nx"], "ny": w["ny"], "status": st["status"], "steps": st["steps"],
-            "rejected": st["rejected"], "t_over_t_end": st["t"] / t_end, "nu_mean": st["nu_mean"],
-            "nu_std": st["nu_std"], "E1": e1, "Einf": einf, "wall_s": wall,
-            "gcell_s": w["nx"] * w["ny"] * st["steps"] / wall / 1e9}
+    out = {"theta": theta, "eta": eta, "nu_W": nu, "reading": reading, "precision": precision,
+           "domain": "mobile" if mobile else "fixed",
+           "nx": w["nx"], "ny": w["ny"], "status": st["status"], "steps": st["steps"],
+           "rejected": st["rejected"], "t_over_t_end": st["t"] / t_end, "nu_mean": st["nu_mean"],
+           "nu_std": st["nu_std"], "E1": e1, "Einf": einf, "wall_s": wall,
+           "gcell_s": w["nx"] * w["ny"] * st["steps"] / wall / 1e9}
+    if window is not None:
+        out["x_off"] = int(ws.x_off)
+    return out
 
 
 def summarize(rows):
@@ -86,6 +107,7 @@ def main(argv):
     which = argv[1] if len(argv) > 1 else "all"
     reading = argv[2] if len(argv) > 2 else "rise"
     precision = argv[3] if len(argv) > 3 else "f64"
+    mobile = len(argv) > 4 and argv[4] == "window"
     if which == "all":
         cases = list(itertools.product(THETAS, ETAS, NUS))
     else:
@@ -93,7 +115,7 @@ def main(argv):
         cases = [(float(th), int(eta), float(nu))]
     rows = []
     for theta, eta, nu in cases:
-        r = run(theta, eta, nu, reading, precision)
+        r = run(theta, eta, nu, reading, precision, mobile)
         rows.append(r)
         print(json.dumps(r), flush=True)
     for srow in summarize(rows):

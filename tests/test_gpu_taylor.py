@@ -107,3 +107,34 @@ def test_moving_domain_taylor_vs_oracle(precision, tol):
         _say(f"  moved-domain errors: device {e1:.6e} {einf:.6e}, host {h1:.6e} {hinf:.6e}")
         assert abs(e1 - h1) <= 1e-12 * h1 and abs(einf - hinf) <= 1e-12 * hinf
     sim.fvna_destroy()
+
+
+GOLDEN_MOBILE = __import__("os").path.join(__import__("os").path.dirname(__file__), "golden",
+                                           "table1_mobile_oracle.txt")
+
+
+def test_table1_oblique_rows_on_the_mobile_domain_vs_oracle():
+    """Rows of the Table 1 study on the mobile domain (taylor_report's window
+    mode) against the FP64 oracle's run_window on the same set-up
+    (tests/golden/table1_mobile_oracle.txt, written by make_table1_mobile.py
+    from the oracle only): theta_T = pi/8 and pi/4, eta = 5, 10, 20,
+    nu_W = 0.9.  Per run the number of steps and the domain's offset are equal
+    and E1, Einf of eq. (error) agree to 1e-8 relative; so do the convergence
+    rates of E1 and Einf over the three meshes."""
+    from paper_1311_3004_amd import taylor_report as tr
+    rows = [l.split() for l in open(GOLDEN_MOBILE) if l.strip() and not l.startswith("#")]
+    got = {}
+    for th, eta, nu, steps, xo, e1, einf in rows:
+        th, eta, nu, e1, einf = float(th), int(eta), float(nu), float(e1), float(einf)
+        _say(f"case: Table 1 mobile theta={th:.4f} eta={eta} nu={nu}")
+        r = tr.run(th, eta, nu, mobile=True)
+        _say(f"  GPU E1 {r['E1']:.6e} Einf {r['Einf']:.6e}; oracle {e1:.6e} {einf:.6e}")
+        assert r["status"] == 0 and r["steps"] == int(steps) and r["x_off"] == int(xo) > 0
+        assert abs(r["E1"] - e1) <= 1e-8 * e1 and abs(r["Einf"] - einf) <= 1e-8 * einf
+        got.setdefault(th, []).append((eta, r["E1"], r["Einf"], e1, einf))
+    for th, pts in got.items():
+        x = np.log([p[0] for p in pts])
+        for k in (1, 2):
+            rate_gpu = -np.polyfit(x, np.log([p[k] for p in pts]), 1)[0]
+            rate_orc = -np.polyfit(x, np.log([p[k + 2] for p in pts]), 1)[0]
+            assert abs(rate_gpu - rate_orc) <= 1e-6 and 0.8 < rate_gpu < 2.5
