@@ -364,6 +364,20 @@ fvna_status fvna_batch_get_state(fvna_batch* b, int32_t k, double* rho_p, double
                                  double* mom_y);
 fvna_status fvna_batch_get_stats(fvna_batch* b, int32_t k, fvna_stats* s);
 fvna_status fvna_batch_time_step_kernel(fvna_batch* b, int32_t reps, double* ms_per_launch);
+/* Choose the segment height of the members by timing the batched step kernel
+ * on the batch itself: members are grouped in size classes by ny (powers of
+ * two); for each class in turn the heights 32, 48, 64, 96, 128, 192, 256 are
+ * timed with the other classes fixed and the fastest kept.  Members created
+ * with their own tile_rows keep it.  The choice is kept in-process for the
+ * batch's composition (precision, geometry and every member's nx, ny in
+ * order) and taken by later fvna_batch_create calls with the same
+ * composition.  Results are bitwise independent of the heights.  Waits for
+ * the stream; the timing launches recompute the attempt the next step makes,
+ * so the simulations are unchanged.  tile_rows (may be NULL) receives n
+ * heights. */
+fvna_status fvna_batch_autotune(fvna_batch* b, int32_t* tile_rows);
+/* The n members' segment heights. */
+fvna_status fvna_batch_get_tile_rows(fvna_batch* b, int32_t* tile_rows);
 void fvna_batch_destroy(fvna_batch* b);
 
 #ifdef __cplusplus

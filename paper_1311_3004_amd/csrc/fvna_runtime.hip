@@ -290,25 +290,38 @@ struct RecDesc {
     double rho0, t_unit;
 };
 
+// Controller and recorder in one launch (one block): thread 0 decides the
+// attempt (control), hands the updated clock to the block through LDS, and
+// the block records the row (a separate recorder launch after k_ctrl cost as
+// much as the controller itself, 4.6 us per attempt).
 template <typename S, typename T>
-__global__ __launch_bounds__(256) void k_record(SimDesc d, RecDesc r)
+__global__ __launch_bounds__(256) void k_ctrl_record(SimDesc d, RecDesc r)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= d.nx) return;
-    const Clock* clk = d.clk;
-    const long long k = clk->accepted - r.base - 1;   // index of the latest accepted step
+    __shared__ long long s_acc, s_xoff;
+    __shared__ int s_cur;
+    __shared__ double s_t;
+    if (threadIdx.x == 0) {
+        control_attempt(d.clk, d.fixed_dt, d.cfl_target, d.cfl_max, d.max_retries, 2);
+        const Clock* clk = d.clk;
+        s_acc = clk->accepted;
+        s_xoff = clk->x_off;
+        s_cur = clk->cur;
+        s_t = clk->t;
+    }
+    __syncthreads();
+    const long long k = s_acc - r.base - 1;             // index of the latest accepted step
     if (k < 0) return;
-    const S* R = (const S*)d.buf[clk->cur] + (size_t)r.row * d.pitch;
-    const double rho = (double)Codec<S, T>::ld(R[i], d.scale[0]) * r.rho0;
-    const long long pc = clk->x_off + i;                // path column of this cell
-    if (pc < r.path_len) r.row_max[pc] = fmax(r.row_max[pc], rho);
-    if (pc == r.probe_col && k < r.capacity) {
-        r.probe_t[k] = clk->t * r.t_unit;
-        r.probe_rho[k] = rho;
+    const S* R = (const S*)d.buf[s_cur] + (size_t)r.row * d.pitch;
+    for (int i = threadIdx.x; i < d.nx; i += blockDim.x) {
+        const double rho = (double)Codec<S, T>::ld(R[i], d.scale[0]) * r.rho0;
+        const long long pc = s_xoff + i;
+        if (pc < r.path_len) r.row_max[pc] = fmax(r.row_max[pc], rho);
+        if (pc == r.probe_col && k < r.capacity) {
+            r.probe_t[k] = s_t * r.t_unit;
+            r.probe_rho[k] = rho;
+        }
     }
 }
-
-
 
 // Fixed-order FP64 sums: block b sums rows b, b + NB, ... with a fixed
 // thread stride and a fixed tree; the final pass sums the NB partials.
@@ -604,7 +617,7 @@ struct Launcher {
     void (*exp)(const SimDesc&, double*, int, int, int, int, int, double, hipStream_t);
     void (*sums)(const SimDesc&, const void* state, double* part, double* out, const double* factor, hipStream_t);
     void (*shift)(const SimDesc&, int, hipStream_t);
-    void (*record)(const SimDesc&, const RecDesc&, hipStream_t);
+    void (*ctrl_record)(const SimDesc&, const RecDesc&, hipStream_t);
     void (*taylor_err)(const SimDesc&, const ErrLine&, double*, hipStream_t);
 };
 
@@ -644,8 +657,8 @@ Launcher make_launcher()
         hipLaunchKernelGGL((k_shift<S, T>), dim3((d.pitch + 255) / 256, rows), dim3(256), 0, s, d, ncols);
         hipLaunchKernelGGL(k_flip, dim3(1), dim3(64), 0, s, d.clk, ncols);
     };
-    L.record = [](const SimDesc& d, const RecDesc& r, hipStream_t s) {
-        hipLaunchKernelGGL((k_record<S, T>), dim3((d.nx + 255) / 256), dim3(256), 0, s, d, r);
+    L.ctrl_record = [](const SimDesc& d, const RecDesc& r, hipStream_t s) {
+        hipLaunchKernelGGL((k_ctrl_record<S, T>), dim3(1), dim3(256), 0, s, d, r);
     };
     L.taylor_err = [](const SimDesc& d, const ErrLine& e, double* out, hipStream_t s) {
         hipLaunchKernelGGL((k_taylor_err<S, T>), dim3(1), dim3(256), 0, s, d, e, out);
@@ -711,12 +724,13 @@ struct fvna_ctx {
     double ta_amp_pa = 0.0, ta_x0_m = 0.0;
 };
 
-// One attempt on stream s: the step, the CFL decision, the recorder if any.
+// One attempt on stream s: the step, then the CFL decision (and the recorder,
+// in the same launch, if any).
 static void launch_attempt(fvna_ctx* c, hipStream_t s)
 {
     c->L.step(c->d, 0, s);
-    hipLaunchKernelGGL(k_ctrl, dim3(1), dim3(64), 0, s, c->d);
-    if (c->recording) c->L.record(c->d, c->rec, s);
+    if (c->recording) c->L.ctrl_record(c->d, c->rec, s);
+    else hipLaunchKernelGGL(k_ctrl, dim3(1), dim3(64), 0, s, c->d);
 }
 
 // Destroy the captured graph after every launch of it already enqueued on the
@@ -1383,9 +1397,35 @@ struct fvna_batch {
     SimDesc* d_desc = nullptr;      // device copy of the descriptors
     TileRef* d_tiles = nullptr;
     int ntiles = 0;
+    int tile_cap = 0;               // TileRefs d_tiles can hold
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
 };
+
+namespace {
+
+// Batch autotune cache: (precision, geometry, the members' (nx, ny) in order)
+// -> the chosen segment height of each member.
+typedef std::tuple<int, int, std::vector<std::pair<int, int>>> BatchKey;
+std::mutex g_btune_mu;
+std::map<BatchKey, std::vector<int>> g_btune;
+
+BatchKey batch_key(const fvna_params* p, int n)
+{
+    std::vector<std::pair<int, int>> g;
+    for (int k = 0; k < n; ++k) g.emplace_back(p[k].nx, p[k].ny);
+    return BatchKey(p[0].precision, p[0].geometry, g);
+}
+
+void batch_tiles(const fvna_batch* b, std::vector<TileRef>& tiles)
+{
+    tiles.clear();
+    for (int k = 0; k < b->n; ++k)
+        for (int sg = 0; sg < b->d[k].segs; ++sg)
+            for (int st = 0; st < b->d[k].strips; ++st) tiles.push_back(TileRef{k, st, sg, 0});
+}
+
+}  // namespace
 
 static fvna_status batch_graph(fvna_batch* b)
 {
@@ -1437,21 +1477,28 @@ fvna_status fvna_batch_create(int32_t n, const fvna_params* per_sim, void* const
     b->n = n;
     b->stream = (hipStream_t)hip_stream;
     b->L = pick_launcher(per_sim[0].precision, per_sim[0].geometry);
-    std::vector<TileRef> tiles;
+    std::vector<int> tuned;
+    {
+        std::lock_guard<std::mutex> g(g_btune_mu);
+        auto it = g_btune.find(batch_key(per_sim, n));
+        if (it != g_btune.end()) tuned = it->second;
+    }
     for (int k = 0; k < n; ++k) {
         const fvna_params& p = per_sim[k];
         b->p.push_back(p);
         SimDesc d;
         // many simulations fill the device in many rounds: moderate segments
-        int tr = p.tile_rows ? p.tile_rows : BATCH_TILE_ROWS;
+        // (or the heights fvna_batch_autotune chose for this composition)
+        int tr = p.tile_rows ? p.tile_rows : (tuned.empty() ? BATCH_TILE_ROWS : tuned[k]);
         char* sc = (char*)bufs[3 * k + 2];
         fill_desc(d, &p, bufs[3 * k], bufs[3 * k + 1], (Clock*)(sc + OFF_CLOCK), tr);
         b->d.push_back(d);
         b->scratch.push_back(sc);
-        for (int sg = 0; sg < d.segs; ++sg)
-            for (int st = 0; st < d.strips; ++st) tiles.push_back(TileRef{k, st, sg, 0});
     }
+    std::vector<TileRef> tiles;
+    batch_tiles(b, tiles);
     b->ntiles = (int)tiles.size();
+    b->tile_cap = b->ntiles;
     auto cleanup = [&]() {
         if (b->d_desc) (void)hipFree(b->d_desc);
         if (b->d_tiles) (void)hipFree(b->d_tiles);
@@ -1578,6 +1625,88 @@ fvna_status fvna_batch_get_stats(fvna_batch* b, int32_t k, fvna_stats* st)
     if (s) return s;
     if (dev != FVNA_OK) g_err = msg;
     return dev;
+}
+
+// Upload the descriptors and tile table after a change of segment heights
+// (the captured graph holds the old tile count: dropped).
+static fvna_status batch_retile(fvna_batch* b)
+{
+    if (b->exec || b->graph) {
+        HIP_TRY(hipStreamSynchronize(b->stream));
+        if (b->exec) (void)hipGraphExecDestroy(b->exec);
+        if (b->graph) (void)hipGraphDestroy(b->graph);
+        b->exec = nullptr;
+        b->graph = nullptr;
+    }
+    std::vector<TileRef> tiles;
+    batch_tiles(b, tiles);
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    if ((int)tiles.size() > b->tile_cap) {
+        TileRef* t = nullptr;
+        HIP_TRY(hipMalloc(&t, sizeof(TileRef) * tiles.size()));
+        (void)hipFree(b->d_tiles);
+        b->d_tiles = t;
+        b->tile_cap = (int)tiles.size();
+    }
+    HIP_TRY(hipMemcpy(b->d_tiles, tiles.data(), sizeof(TileRef) * tiles.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(b->d_desc, b->d.data(), sizeof(SimDesc) * b->n, hipMemcpyHostToDevice));
+    b->ntiles = (int)tiles.size();
+    return FVNA_OK;
+}
+
+fvna_status fvna_batch_autotune(fvna_batch* b, int32_t* tile_rows)
+{
+    if (!b) return fail(FVNA_E_INVALID, "batch is NULL");
+    // size classes by ny (powers of two); members with their own tile_rows keep it
+    std::map<int, std::vector<int>> cls;
+    for (int k = 0; k < b->n; ++k)
+        if (b->p[k].tile_rows == 0) {
+            int c = 0;
+            while ((2 << c) <= b->p[k].ny) ++c;
+            cls[c].push_back(k);
+        }
+    const int cand[] = {32, 48, 64, 96, 128, 192, 256};
+    auto time_it = [&](double* ms) -> fvna_status {
+        fvna_status s = fvna_batch_time_step_kernel(b, 1, ms);      // warm-up
+        if (!s) s = fvna_batch_time_step_kernel(b, 5, ms);
+        return s;
+    };
+    // one pass of coordinate descent over the classes, smallest grids first
+    for (auto& kv : cls) {
+        const int cur = b->d[kv.second[0]].tile_rows;
+        double best = 1e30;
+        int best_tr = cur;
+        for (int tr : cand) {
+            bool useful = false;
+            for (int k : kv.second) useful = useful || tr < 2 * b->p[k].ny;
+            if (!useful) continue;
+            for (int k : kv.second) set_segments(b->d[k], tr);
+            fvna_status s = batch_retile(b);
+            double ms = 0.0;
+            if (!s) s = time_it(&ms);
+            if (s) return s;
+            if (ms < best) { best = ms; best_tr = tr; }
+        }
+        for (int k : kv.second) set_segments(b->d[k], best_tr);
+    }
+    fvna_status s = batch_retile(b);
+    if (s) return s;
+    std::vector<int> chosen(b->n);
+    for (int k = 0; k < b->n; ++k) chosen[k] = b->d[k].tile_rows;
+    {
+        std::lock_guard<std::mutex> g(g_btune_mu);
+        g_btune[batch_key(b->p.data(), b->n)] = chosen;
+    }
+    if (tile_rows)
+        for (int k = 0; k < b->n; ++k) tile_rows[k] = chosen[k];
+    return FVNA_OK;
+}
+
+fvna_status fvna_batch_get_tile_rows(fvna_batch* b, int32_t* tile_rows)
+{
+    if (!b || !tile_rows) return fail(FVNA_E_INVALID, "NULL argument");
+    for (int k = 0; k < b->n; ++k) tile_rows[k] = b->d[k].tile_rows;
+    return FVNA_OK;
 }
 
 fvna_status fvna_batch_time_step_kernel(fvna_batch* b, int32_t reps, double* ms_per_launch)

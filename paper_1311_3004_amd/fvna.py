@@ -36,7 +36,7 @@ EXPORTS = [
     "fvna_get_stats", "fvna_sums", "fvna_sums_noalloc", "fvna_taylor_errors", "fvna_time_step_kernel", "fvna_autotune", "fvna_get_tile_rows",
     "fvna_last_error", "fvna_destroy", "fvna_batch_create", "fvna_batch_set_state",
     "fvna_batch_step", "fvna_batch_sync", "fvna_batch_get_state", "fvna_batch_get_stats",
-    "fvna_batch_time_step_kernel", "fvna_batch_destroy",
+    "fvna_batch_time_step_kernel", "fvna_batch_autotune", "fvna_batch_get_tile_rows", "fvna_batch_destroy",
 ]
 
 
@@ -128,6 +128,8 @@ def _load():
         "fvna_batch_get_state": (st, [vp, i32, dp, dp, dp]),
         "fvna_batch_get_stats": (st, [vp, i32, P(fvna_stats)]),
         "fvna_batch_time_step_kernel": (st, [vp, i32, dp]),
+        "fvna_batch_autotune": (st, [vp, P(i32)]),
+        "fvna_batch_get_tile_rows": (st, [vp, P(i32)]),
         "fvna_batch_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
@@ -386,6 +388,16 @@ class Batch:
         ms = ctypes.c_double()
         check(lib.fvna_batch_time_step_kernel(self.handle, int(reps), ctypes.byref(ms)))
         return ms.value
+
+    def fvna_batch_autotune(self):
+        out = (ctypes.c_int32 * self.n)()
+        check(lib.fvna_batch_autotune(self.handle, out))
+        return list(out)
+
+    def fvna_batch_get_tile_rows(self):
+        out = (ctypes.c_int32 * self.n)()
+        check(lib.fvna_batch_get_tile_rows(self.handle, out))
+        return list(out)
 
     def fvna_batch_destroy(self):
         if getattr(self, "handle", None):

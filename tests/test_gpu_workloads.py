@@ -117,6 +117,35 @@ def test_batched_equals_separate_contexts_bitwise(precision):
     B.fvna_batch_destroy()
 
 
+def test_batch_autotune_changes_speed_not_results():
+    """fvna_batch_autotune picks heights per size class by timing the batch;
+    the batch then still equals separate contexts bit for bit, and a new batch
+    of the same composition starts with the chosen heights."""
+    from paper_1311_3004_amd import fvna
+    sims = _batch_sims()
+    plist = [fvna.make_params(x["nx"], x["ny"], x["dx"], x["medium"], bc=x["bc"], precision="f32")
+             for x in sims]
+    _say(f"case: batch autotune, {len(sims)} members")
+    B = fvna.Batch(plist)
+    for k, x in enumerate(sims):
+        B.fvna_batch_set_state(k, *x["state"])
+    tr = B.fvna_batch_autotune()
+    assert tr == B.fvna_batch_get_tile_rows() and all(t in (32, 48, 64, 96, 128, 192, 256) for t in tr)
+    B.fvna_batch_step(40)
+    B.fvna_batch_sync()
+    for k, x in enumerate(sims):
+        s = fvna.Sim(plist[k])
+        s.fvna_set_state(*x["state"])
+        s.fvna_step(40)
+        for u, v in zip(s.fvna_get_state(), B.fvna_batch_get_state(k)):
+            assert np.array_equal(u, v)
+        s.fvna_destroy()
+    B.fvna_batch_destroy()
+    B2 = fvna.Batch(plist)
+    assert B2.fvna_batch_get_tile_rows() == tr
+    B2.fvna_batch_destroy()
+
+
 def test_autotune_changes_speed_not_results():
     from paper_1311_3004_amd import fvna, inputs
     w = inputs.c2_pulse_fp32(1024, 768)
@@ -162,10 +191,16 @@ def _focal(w, res, prec, zstar=None):
     return f
 
 
+# The error budget of each storage precision on this workload against the
+# FP64 run (focal p+ and p- relative, harmonics 1-5 relative, shock-front
+# shift in cells); None: the precision does not resolve that quantity and no
+# bound is claimed.  FP16 storage resolves the focal pressures, the first
+# three harmonics and the front; BF16 (8-bit significand) only the focal
+# pressures -- its harmonics are off by 13-270% and its front by 4 cells.
 @pytest.mark.parametrize("prec,tol_peak,tol_h,tol_front", [
     ("f32", 1e-4, [1e-4, 1e-3, 1e-3, 1e-3, 5e-3], 0.05),
-    ("f32_f16store", 5e-3, [5e-3, 2e-2, 5e-2, 0.2, 0.3], 1.0),
-    ("f32_bf16store", 5e-2, [0.3, 0.6, 2.0, 5.0, 5.0], 8.0),
+    ("f32_f16store", 5e-3, [5e-3, 1e-2, 3e-2, None, None], 0.5),
+    ("f32_bf16store", 5e-3, [None] * 5, None),
 ])
 def test_hifu_axisym_precisions_against_fp64(hifu_runs, prec, tol_peak, tol_h, tol_front):
     from paper_1311_3004_amd import diagnostics as dg
@@ -179,8 +214,10 @@ def test_hifu_axisym_precisions_against_fp64(hifu_runs, prec, tol_peak, tol_h, t
          f"harmonics {['%.1e' % h for h in c['harmonics_rel']]} front {got['front'] - ref['front']:+.3f} cells")
     assert c["p_plus_rel"] <= tol_peak and c["p_minus_rel"] <= tol_peak
     for h, tol in zip(c["harmonics_rel"], tol_h):
-        assert h <= tol
-    assert abs(got["front"] - ref["front"]) <= tol_front
+        if tol is not None:
+            assert h <= tol
+    if tol_front is not None:
+        assert abs(got["front"] - ref["front"]) <= tol_front
 
 
 ETAS = (20, 40, 80)
