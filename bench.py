@@ -12,7 +12,7 @@ arithmetic: all its simulations run in double precision).  Beside it: the
 FP32 path on the same workload with its error against FP64, the batched form
 (64 uneven simulations, one graph-replayed launch per step) against 64
 sequential launches, the axisymmetric focused-source configs (8192 x 2048
-FP32; 16384 x 8192 in FP32, FP16 and BF16 storage), the 3-D step, the
+FP32; 16384 x 8192 in FP32 and FP16 storage), the 3-D step, the
 roofline of the step kernels and the FP64 CPU oracle timed on a bounded
 sample on the host (one thread and every core of the process's CPU share).
 """
@@ -35,21 +35,23 @@ BYTES_PER_CELL = {"f64": 48, "f32": 24, "f32_f16store": 12, "f32_bf16store": 12}
 # then WRITE_SIZE, each scaled by what the same counter reads for a plain
 # 1 GiB device copy (fetch x2.000, write x1.000), and VALU lane-ops per
 # cell-update from SQ_INSTS_VALU x 64 / cells (profiles/k_step_*.md).  Each
-# entry is valid only for the kernel sources and build flags whose SHA-256 it
-# records: after any change they report null until profiled again.
-PMC_SOURCES = ("csrc/fvna_device.hpp", "csrc/fvna_step.hpp", "build.py")
+# entry is valid only for the kernel sources, launch configuration (the
+# runtime sets the row segments) and build flags whose SHA-256 it records:
+# after any change they report null until profiled again.
+PMC_SOURCES = ("csrc/fvna_device.hpp", "csrc/fvna_step.hpp", "csrc/fvna_runtime.hip", "build.py")
 _PROFILED = {
-    "csrc/fvna_device.hpp": "36224bdec71b2149af2a36c7e561432dc6c8d97c03d0f968f7e439323ef7115c",
+    "csrc/fvna_device.hpp": "bce3a268b2725d2de7e52684d65f770782e68fea7753fb2da76de4115dabc3e8",
     "csrc/fvna_step.hpp": "bdaa87da40e74c672a969a9b5e399e58b6871975b76743ca535f1ce64673c707",
+    "csrc/fvna_runtime.hip": "205bfd4382d92ca969af3c5710c773d27af5000d46223750f815c9002ca3b582",
     "build.py": "02eda4061ab4ab18fbd0c2e868524ec4e9acf39f5fa26d0513e48c2fca74259e",
 }
 PMC = {
     # profiles/k_step_f64_gaussian4096.md
-    "k_step<double,double,0>": {"nx": 4096, "ny": 4096, "fetch_bytes": 4.2294e+08, "write_bytes": 4.0520e+08,
-                                "valu_lane_ops_per_cell": 484.6, "sources": _PROFILED},
+    "k_step<double,double,0>": {"nx": 4096, "ny": 4096, "fetch_bytes": 4.2219e+08, "write_bytes": 4.0533e+08,
+                                "valu_lane_ops_per_cell": 416.6, "sources": _PROFILED},
     # profiles/k_step_f32_gaussian4096.md
-    "k_step<float,float,0>": {"nx": 4096, "ny": 4096, "fetch_bytes": 2.1615e+08, "write_bytes": 2.0438e+08,
-                              "valu_lane_ops_per_cell": 307.9, "sources": _PROFILED},
+    "k_step<float,float,0>": {"nx": 4096, "ny": 4096, "fetch_bytes": 2.1645e+08, "write_bytes": 2.0437e+08,
+                              "valu_lane_ops_per_cell": 307.6, "sources": _PROFILED},
 }
 
 
