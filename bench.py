@@ -279,6 +279,7 @@ def batched_leg(fvna, inputs, nb):
     B = fvna.Batch(plist)
     for k, x in enumerate(sims):
         B.fvna_batch_set_state(k, *x["state"])
+    B.fvna_batch_time_step_kernel(2)                # warm-up
     ms_default = B.fvna_batch_time_step_kernel(5)
     tuned = B.fvna_batch_autotune()
     classes = {}
