@@ -44,7 +44,8 @@ struct Desc3 {
     int n[3];                  // nx, ny, nz
     int pitch;                 // elements per x1 row (padded to 256 bytes)
     int strips12, segs12, rows12;   // x1-x2 tiles: 60-column strips, row segments of rows12
-    int strips64, segs3, planes3;   // x3 and source tiles: 64-column strips, z segments of planes3
+    int strips64, segs3, planes3;   // x3 tiles: 64-column strips, z segments of planes3
+    int segs4, planes4;             // source tiles: z segments of planes4 (blocks of four rows)
     long long plane;           // elements per field = pitch * ny * nz
     int bc[6];
     int fixed_dt, max_retries;
@@ -455,48 +456,60 @@ __global__ __launch_bounds__(256) void k3_sweep3(Desc3 d, int force)
 
 // ---------------------------------------------------------------------------
 // Source (3-D form of eq. fs:source, forward Euler): M_c += dt delta~ lap(u_c),
-// 7-point Laplacian of u_c = M_c / (1 + R), R unchanged.  Lane = column
-// strip * 64 + lane, row j, planes k0 .. k1 - 1.  Neighbours outside the grid
-// by the side rules (mirrored normal velocity).
+// 7-point Laplacian of u_c = M_c / (1 + R), R unchanged.  A block of four
+// wavefronts takes rows 4g .. 4g + 3 of one 64-column strip over planes
+// k0 .. k1 - 1: lane = column, wave = row.  Per plane each wave publishes its
+// row's velocities in LDS (waves 0 and 3 also the rows 4g - 1 and 4g + 4),
+// and after one barrier reads its x2 neighbours there; x3 neighbours are
+// carried in registers, x1 neighbours come over DPP (the strip's end lanes
+// load theirs).  Neighbours outside the grid follow the side rules (mirrored
+// normal velocity); rows past ny are such ghost rows and are never stored.
+// Every wave of a block runs the same number of barriers: the only early
+// exits come before the loop and hold for the whole block.
 // ---------------------------------------------------------------------------
 template <typename T> struct Vel { T u1, u2, u3; };
 
 template <typename T>
 __global__ __launch_bounds__(256) void k3_source(Desc3 d, int force)
 {
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int tile = xcd_block(blockIdx.x, gridDim.x) * WAVES_PER_BLOCK + wave;
-    const int ntiles = d.strips64 * d.n[1] * d.segs3;
-    if (tile >= ntiles) return;
+    __shared__ T ys[2][6][3][WAVE];                 // [plane parity][row 4g-1 .. 4g+4][component][lane]
+    const int ngroups = (d.n[1] + 3) / 4;
+    const int b = xcd_block(blockIdx.x, gridDim.x);
+    if (b >= d.strips64 * ngroups * d.segs4) return;        // the whole block
     const Clock* clk = d.clk;
-    if (!step_owed(clk, force)) return;
-    const int strip = tile % d.strips64;
-    const int j = (tile / d.strips64) % d.n[1];
-    const int seg = tile / (d.strips64 * d.n[1]);
-    const int nx = d.n[0], nz = d.n[2];
+    if (!step_owed(clk, force)) return;                       // the whole block (same clock)
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int strip = b % d.strips64;
+    const int g = (b / d.strips64) % ngroups;
+    const int seg = b / (d.strips64 * ngroups);
+    const int nx = d.n[0], ny = d.n[1], nz = d.n[2];
     const int lane = threadIdx.x & (WAVE - 1);
     const int col = strip * WAVE + lane;
+    const int j = 4 * g + wave;
     // lanes past the last column hold the x+ ghost by the side rule (the
-    // lane after the last column is that column's right neighbour)
-    bool oneg;
+    // lane after the last column is that column's right neighbour); rows past
+    // the last row likewise hold the y+ ghost
+    bool oneg, jneg;
     const int scol = side_map(d, 0, col, oneg);
-    const int k0 = seg * d.planes3, k1 = min(k0 + d.planes3, nz);
+    const int sj = side_map(d, 1, j, jneg);
+    const int k0 = seg * d.planes4, k1 = min(k0 + d.planes4, nz);
     const T dt = (T)clk->dt;
     const int cur = clk->cur;
     const T* in = (const T*)d.buf[cur == 0 ? 2 : cur - 1];
     T* out = (T*)d.buf[cur == 2 ? 0 : cur + 1];
     const T kd = dt * (T)d.delta;
     const size_t pl = (size_t)d.plane;
-    const size_t zstride = (size_t)d.n[1] * (size_t)d.pitch;
-    // x neighbours of the edge lanes: lane 0 needs column col - 1, lane 63
-    // column col + 1 (others come over DPP); y neighbours: rows j - 1, j + 1
+    const size_t zstride = (size_t)ny * (size_t)d.pitch;
     const bool edge = lane == 0 || lane == WAVE - 1;
-    bool eneg = false, ylneg, yhneg;
+    bool eneg = false;
     int ecol = scol;
     if (lane == 0) ecol = side_map(d, 0, col - 1, eneg);
     else if (lane == WAVE - 1) ecol = side_map(d, 0, col + 1, eneg);
-    const int jl = side_map(d, 1, j - 1, ylneg), jh = side_map(d, 1, j + 1, yhneg);
-    const size_t rowj = (size_t)j * (size_t)d.pitch;
+    // halo rows: wave 0 publishes row 4g - 1, wave 3 row 4g + 4
+    const bool halo = wave == 0 || wave == 3;
+    bool hneg = false;
+    const int hj = halo ? side_map(d, 1, wave == 0 ? 4 * g - 1 : 4 * g + 4, hneg) : sj;
+    const int hslot = wave == 0 ? 0 : 5;
     // raw cell at element offset o with the mirrored components negated
     auto raw = [&](size_t o, bool neg1, bool neg2, bool neg3) -> Q4<T> {
         Q4<T> q{in[o], in[pl + o], in[2 * pl + o], in[3 * pl + o]};
@@ -513,30 +526,45 @@ __global__ __launch_bounds__(256) void k3_source(Desc3 d, int force)
     auto own = [&](int v) -> Q4<T> {
         bool zneg;
         const int sk = side_map(d, 2, v, zneg);
-        return raw((size_t)sk * zstride + rowj + (size_t)scol, oneg, false, zneg);
+        return raw((size_t)sk * zstride + (size_t)sj * (size_t)d.pitch + (size_t)scol, oneg, jneg, zneg);
     };
-    // its x (edge lanes only) and y neighbours in plane v (v inside the grid
-    // when used; clamped otherwise)
-    struct Nb { Q4<T> e, yl, yh; };
-    auto nbrs = [&](int v) -> Nb {
+    // the halo row (waves 0, 3) and the end lanes' x neighbours in plane v
+    // (v inside the grid when used; clamped otherwise)
+    const Q4<T> zero{T(0), T(0), T(0), T(0)};
+    auto side_cells = [&](int v, Q4<T>& h, Q4<T>& e) {
         const size_t zo = (size_t)min(max(v, 0), nz - 1) * zstride;
-        Nb b;
-        b.e = Q4<T>{T(0), T(0), T(0), T(0)};
-        if (edge) b.e = raw(zo + rowj + (size_t)ecol, eneg, false, false);
-        b.yl = raw(zo + (size_t)jl * (size_t)d.pitch + (size_t)scol, false, ylneg, false);
-        b.yh = raw(zo + (size_t)jh * (size_t)d.pitch + (size_t)scol, false, yhneg, false);
-        return b;
+        h = zero;
+        e = zero;
+        if (halo) h = raw(zo + (size_t)hj * (size_t)d.pitch + (size_t)scol, oneg, hneg, false);
+        if (edge) e = raw(zo + (size_t)sj * (size_t)d.pitch + (size_t)ecol, eneg, jneg, false);
     };
-    // loads run ahead: this lane's cells two planes, the neighbours one plane
-    Q4<T> q0 = own(k0), q1 = own(k0 + 1);
-    Nb nb = nbrs(k0);
+    // loads run ahead: this lane's cells two planes, the side cells one plane
+    Q4<T> q0 = own(k0), q1 = own(k0 + 1), hq, eq;
+    side_cells(k0, hq, eq);
     Vel<T> ub = vel(own(k0 - 1)), uc = vel(q0);
 #pragma unroll 1
     for (int k = k0; k < k1; ++k) {
         const Q4<T> q2 = own(k + 2);
-        const Nb nb1 = nbrs(k + 1);
+        Q4<T> hq1, eq1;
+        side_cells(k + 1, hq1, eq1);
         const Vel<T> ua = vel(q1);
-        const Vel<T> e = vel(nb.e), yl = vel(nb.yl), yh = vel(nb.yh);
+        // publish plane k's velocities of this wave's row (and the halo row)
+        T (*slot)[3][WAVE] = ys[k & 1];
+        slot[wave + 1][0][lane] = uc.u1;
+        slot[wave + 1][1][lane] = uc.u2;
+        slot[wave + 1][2][lane] = uc.u3;
+        if (halo) {
+            const Vel<T> hv = vel(hq);
+            slot[hslot][0][lane] = hv.u1;
+            slot[hslot][1][lane] = hv.u2;
+            slot[hslot][2][lane] = hv.u3;
+        }
+        // every wave has published plane k; the slot written next (plane
+        // k + 1) was last read before the previous barrier
+        __syncthreads();
+        const Vel<T> yl{slot[wave][0][lane], slot[wave][1][lane], slot[wave][2][lane]};
+        const Vel<T> yh{slot[wave + 2][0][lane], slot[wave + 2][1][lane], slot[wave + 2][2][lane]};
+        const Vel<T> e = vel(eq);
         Vel<T> xl, xh;
         xl.u1 = from_lo(uc.u1); xl.u2 = from_lo(uc.u2); xl.u3 = from_lo(uc.u3);
         xh.u1 = from_hi(uc.u1); xh.u2 = from_hi(uc.u2); xh.u3 = from_hi(uc.u3);
@@ -549,8 +577,8 @@ __global__ __launch_bounds__(256) void k3_source(Desc3 d, int force)
         const T l1 = lap(uc.u1, xl.u1, xh.u1, yl.u1, yh.u1, ub.u1, ua.u1);
         const T l2 = lap(uc.u2, xl.u2, xh.u2, yl.u2, yh.u2, ub.u2, ua.u2);
         const T l3 = lap(uc.u3, xl.u3, xh.u3, yl.u3, yh.u3, ub.u3, ua.u3);
-        if (col < nx) {
-            const size_t o = (size_t)k * zstride + rowj + (size_t)col;
+        if (col < nx && j < ny) {
+            const size_t o = (size_t)k * zstride + (size_t)j * (size_t)d.pitch + (size_t)col;
             out[o] = q0.R;
             out[pl + o] = fma_(kd, l1, q0.n);
             out[2 * pl + o] = fma_(kd, l2, q0.a);
@@ -560,7 +588,8 @@ __global__ __launch_bounds__(256) void k3_source(Desc3 d, int force)
         uc = ua;
         q0 = q1;
         q1 = q2;
-        nb = nb1;
+        hq = hq1;
+        eq = eq1;
     }
 }
 
@@ -712,7 +741,8 @@ void launch_sweeps(const Desc3& d, int force, hipStream_t s, bool source)
     const int t3 = d.strips64 * d.n[1] * d.segs3;
     hipLaunchKernelGGL(k3_sweep12<T>, dim3((t12 + 3) / 4), dim3(256), 0, s, d, force);
     hipLaunchKernelGGL(k3_sweep3<T>, dim3((t3 + 3) / 4), dim3(256), 0, s, d, force);
-    if (source) hipLaunchKernelGGL(k3_source<T>, dim3((t3 + 3) / 4), dim3(256), 0, s, d, force);
+    const int tsrc = d.strips64 * ((d.n[1] + 3) / 4) * d.segs4;    // blocks of four rows
+    if (source) hipLaunchKernelGGL(k3_source<T>, dim3(tsrc), dim3(256), 0, s, d, force);
 }
 
 template <typename T>
@@ -831,6 +861,11 @@ fvna_status fvna3_create(const fvna3_params* p, void* buf_a, void* buf_b, void* 
     d.strips64 = (p->nx + WAVE - 1) / WAVE;
     d.planes3 = seg_len((long long)d.strips64 * p->ny, p->nz, cus, waves);
     d.segs3 = (p->nz + d.planes3 - 1) / d.planes3;
+    // the source kernel's blocks hold one plane's rows in LDS and are light:
+    // half the x3 sweep's z-segments, twice its waves (256^3 FP32: source
+    // blocks over 64 / 32 / 16 planes 0.486 / 0.469 / 0.473 ms per step)
+    d.planes4 = std::max(8, (d.planes3 + 1) / 2);
+    d.segs4 = (p->nz + d.planes4 - 1) / d.planes4;
     for (int k = 0; k < 6; ++k) d.bc[k] = p->bc[k];
     d.fixed_dt = p->fixed_dt ? 1 : 0;
     d.max_retries = p->max_retries;
