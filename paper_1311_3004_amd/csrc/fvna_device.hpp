@@ -368,10 +368,20 @@ template <> struct Cfl<double> {
 // evaluated as psi = phi/2 = max(0, min((1 + theta)/4, 1, theta)).  Halving
 // is exact, and hr_split doubles the factor psi multiplies, so the products
 // round exactly as they would with phi.
+// (1 + theta)/4: FP64 as ldexp(theta + 1, -2) -- 0.25 is not an inline
+// constant of the FP64 instructions, and the compiler rebuilt it in two
+// registers for every call; 1.0 and the exponent are inline, and the scaling
+// is exact, so the value is bitwise that of fma(0.25, theta, 0.25).
+template <typename T>
+__device__ __forceinline__ T quarter_1p(T th)
+{
+    if constexpr (sizeof(T) == 8) return __builtin_ldexp(th + T(1), -2);
+    else return fma_(T(0.25), th, T(0.25));
+}
 template <typename T>
 __device__ __forceinline__ T mc_half(T th)
 {
-    return max_(T(0), min_(min_(fma_(T(0.25), th, T(0.25)), T(1)), th));
+    return max_(T(0), min_(min_(quarter_1p(th), T(1)), th));
 }
 
 // Products W^p_a . W^p_b of the waves of two neighbouring interfaces for the
