@@ -21,8 +21,9 @@ def test_taylor_errors_on_device_match_host(theta):
     """fvna_taylor_errors (device, FP64, fixed order) against
     diagnostics.taylor_errors (numpy) on the exported state: the same line
     cells, the same reference.  The two differ only by rounding: the device's
-    and the C library's tanh may differ in the last bit, and the export
-    rounds R through rho0, a few 1e-23 on errors of 1e-9 and more."""
+    and the C library's tanh may differ in the last bit, the export rounds R
+    through rho0, and the sums run in different orders; measured relative
+    differences are below 1e-14, the bound is twice that."""
     from paper_1311_3004_amd import diagnostics as dg, fvna, inputs
     w = inputs.taylor_oblique(10, theta, precision="f64")
     _say(f"case: taylor errors theta={theta:.4f} {w['nx']}x{w['ny']}")
@@ -33,10 +34,11 @@ def test_taylor_errors_on_device_match_host(theta):
     e1, einf = s.fvna_taylor_errors(w["front0_m"][0], w["front0_m"][1], hl)
     rp, _, _ = s.fvna_get_state()
     h1, hinf = dg.taylor_errors(w, st["t"], rp / w["medium"]["rho0"])
-    _say(f"  device E1 {e1:.6e} Einf {einf:.6e}; host {h1:.6e} {hinf:.6e}")
+    _say(f"  device E1 {e1:.6e} Einf {einf:.6e}; host {h1:.6e} {hinf:.6e}; "
+         f"rel diff {abs(e1 - h1) / h1:.2e} {abs(einf - hinf) / hinf:.2e}")
     assert 1e-6 < h1 < 1.0 and 1e-6 < hinf < 2.0
-    assert abs(e1 - h1) <= 1e-12 * h1
-    assert abs(einf - hinf) <= 1e-12 * hinf
+    assert abs(e1 - h1) <= 2e-14 * h1
+    assert abs(einf - hinf) <= 2e-14 * hinf
     with pytest.raises(fvna.FvnaError):
         s.fvna_taylor_errors(w["front0_m"][0], w["front0_m"][1], -1.0)
     with pytest.raises(fvna.FvnaError):          # the line far outside the domain
@@ -104,8 +106,9 @@ def test_moving_domain_taylor_vs_oracle(precision, tol):
               "nx": nx, "ny": ny, "taylor": {"x0_m": x0 * dx}, "amplitude": amp, "tanh_unit_m": width * dx}
         e1, einf = sim.fvna_taylor_errors(x0 * dx, 0.0, 5.0 * wl["unit_m"])
         h1, hinf = dg.taylor_errors(wl, st["t"], g[0], x_off=int(ws.x_off))
-        _say(f"  moved-domain errors: device {e1:.6e} {einf:.6e}, host {h1:.6e} {hinf:.6e}")
-        assert abs(e1 - h1) <= 1e-12 * h1 and abs(einf - hinf) <= 1e-12 * hinf
+        _say(f"  moved-domain errors: device {e1:.6e} {einf:.6e}, host {h1:.6e} {hinf:.6e}; "
+             f"rel diff {abs(e1 - h1) / h1:.2e} {abs(einf - hinf) / hinf:.2e}")
+        assert abs(e1 - h1) <= 2e-14 * h1 and abs(einf - hinf) <= 2e-14 * hinf
     sim.fvna_destroy()
 
 
