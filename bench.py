@@ -34,7 +34,11 @@ BYTES_PER_CELL = {"f64": 48, "f32": 24, "f32_f16store": 12, "f32_bf16store": 12}
 # rocprofv3 --pmc runs of this script: HBM bytes per launch from FETCH_SIZE,
 # then WRITE_SIZE, each scaled by what the same counter reads for a plain
 # 1 GiB device copy (fetch x2.000, write x1.000), and VALU lane-ops per
-# cell-update from SQ_INSTS_VALU x 64 / cells (profiles/k_step_*.md).  Each
+# cell-update from SQ_INSTS_VALU x 64 / cells, and SIMD issue cycles per
+# cell-update from SQ_ACTIVE_INST_VALU (quad-cycles, summed over waves) x 4 /
+# cells, which also counts the extra cycles of transcendental instructions
+# (an FP64 reciprocal estimate holds the SIMD 4 quad-cycles, FP32 2)
+# (profiles/k_step_*.md).  Each
 # entry is valid only for the kernel sources, launch configuration (the
 # runtime sets the row segments) and build flags whose SHA-256 it records:
 # after any change they report null until profiled again.
@@ -48,10 +52,12 @@ _PROFILED = {
 PMC = {
     # profiles/k_step_f64_gaussian4096.md
     "k_step<double,double,0>": {"nx": 4096, "ny": 4096, "fetch_bytes": 4.2197e+08, "write_bytes": 4.0467e+08,
-                                "valu_lane_ops_per_cell": 409.8, "sources": _PROFILED},
+                                "valu_lane_ops_per_cell": 409.8, "valu_issue_cycles_per_cell": 28.42,
+                                "sources": _PROFILED},
     # profiles/k_step_f32_gaussian4096.md
     "k_step<float,float,0>": {"nx": 4096, "ny": 4096, "fetch_bytes": 2.1632e+08, "write_bytes": 2.0434e+08,
-                              "valu_lane_ops_per_cell": 307.6, "sources": _PROFILED},
+                              "valu_lane_ops_per_cell": 307.6, "valu_issue_cycles_per_cell": 20.33,
+                              "sources": _PROFILED},
 }
 
 
@@ -74,6 +80,8 @@ def pmc_entry(kernel, nx, ny):
 # Vector-ALU rate of the chip counted as the profile counts SQ_INSTS_VALU:
 # one wave64 instruction per CU per cycle = 256 CUs x 64 lanes x 2.4 GHz.
 VALU_PEAK_LANE_OPS = 256 * 64 * 2.4e9
+# SIMD cycles available per second: 1024 SIMDs at the 2.4 GHz peak clock.
+SIMD_CYCLES_PER_S = 1024 * 2.4e9
 
 
 def measured_valu(kernel, nx, ny, kernel_s):
@@ -85,8 +93,12 @@ def measured_valu(kernel, nx, ny, kernel_s):
         return None
     ops = e["valu_lane_ops_per_cell"]
     rate = ops * nx * ny / kernel_s
+    cyc = e["valu_issue_cycles_per_cell"]
     return {"lane_ops_per_cell": ops, "achieved": round(rate / 1e12, 2), "peak": round(VALU_PEAK_LANE_OPS / 1e12, 2),
-            "unit": "T lane-ops/s", "frac": round(rate / VALU_PEAK_LANE_OPS, 4)}
+            "unit": "T lane-ops/s", "frac": round(rate / VALU_PEAK_LANE_OPS, 4),
+            # fraction of the launch the SIMDs spend issuing vector instructions
+            # (transcendental cycles included), at the 2.4 GHz peak clock
+            "issue_cycles_per_cell": cyc, "issue_frac": round(cyc * nx * ny / kernel_s / SIMD_CYCLES_PER_S, 4)}
 
 
 def measured_traffic(kernel, nx, ny):
