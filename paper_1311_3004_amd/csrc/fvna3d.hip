@@ -119,37 +119,50 @@ __device__ __forceinline__ T roe4(const Q4<T>& L, T unL, T uaL, T ubL, const Q4<
     return spd;
 }
 
-// W^p . W^p' of two interfaces for the acoustic families (entries 0, 1).
+// Upwind values of two neighbouring interfaces x (below) and y (above) for
+// each other, as wave_cross in two dimensions: tx = alpha_x X for y, ty =
+// alpha_y X for x, X = r^p_x . r^p_y for the acoustic families (entries 0, 1);
+// entries 2, 3: the shear strengths alpha^3, alpha^4 (X = 1).
 template <typename T>
-__device__ __forceinline__ void dots4(const W4<T>& x, const W4<T>& y, T d[2])
+__device__ __forceinline__ void cross4(const W4<T>& x, const W4<T>& y, T tx[4], T ty[4])
 {
-    d[0] = (x.a1 * y.a1) * fma_(x.r1b, y.r1b, fma_(x.r1a, y.r1a, fma_(x.s1, y.s1, T(1))));
-    d[1] = (x.a2 * y.a2) * fma_(x.r2b, y.r2b, fma_(x.r2a, y.r2a, fma_(x.s2, y.s2, T(1))));
-}
-
-// theta = W_up . W / W . W for an acoustic family (no guard: see theta_of).
-template <typename T>
-__device__ __forceinline__ T theta4(T dup, T a, T s, T ra, T rb)
-{
-    return dup * rcp((a * a) * fma_(rb, rb, fma_(ra, ra, fma_(s, s, T(1)))));
+    const T x1 = fma_(x.r1b, y.r1b, fma_(x.r1a, y.r1a, fma_(x.s1, y.s1, T(1))));
+    const T x2 = fma_(x.r2b, y.r2b, fma_(x.r2a, y.r2a, fma_(x.s2, y.s2, T(1))));
+    tx[0] = x.a1 * x1; tx[1] = x.a2 * x2; tx[2] = x.a3; tx[3] = x.a4;
+    ty[0] = y.a1 * x1; ty[1] = y.a2 * x2; ty[2] = y.a3; ty[3] = y.a4;
 }
 
 // Fluctuations plus limited corrections of one interface (eqs. fluc:m,
 // fluc:p, limiter, fv-hr): Gm = A^- dQ + F~ for the cell on the low side,
-// Gp = A^+ dQ - F~ for the cell on the high side.  lo/hi: products with the
-// interface below/above (entries 0, 1) and that interface's alpha^3, alpha^4
-// (entries 2, 3).  The upwind interface is the one below for s >= 0.
+// Gp = A^+ dQ - F~ for the cell on the high side.  lo/hi: upwind values t of
+// the interface below/above (cross4).  The upwind interface is the one below
+// for s >= 0.  The limited products psi alpha as in two dimensions (hr_split):
+// FP64 from u = t / n with one reciprocal of n1 n2, FP32 from
+// theta = t / (alpha n).
 template <typename T>
 __device__ __forceinline__ void hr_split4(const W4<T>& w, const T lo[4], const T hi[4], T dt, T Gm[4], T Gp[4])
 {
     const bool n1 = w.s1 < T(0), n2 = w.s2 < T(0), n3 = w.s3 < T(0);
-    const T ps1 = mc_half(theta4(n1 ? hi[0] : lo[0], w.a1, w.s1, w.r1a, w.r1b));
-    const T ps2 = mc_half(theta4(n2 ? hi[1] : lo[1], w.a2, w.s2, w.r2a, w.r2b));
-    const T ps3 = mc_half((n3 ? hi[2] : lo[2]) * rcp(w.a3));
-    const T ps4 = mc_half((n3 ? hi[3] : lo[3]) * rcp(w.a4));
+    const T t1 = n1 ? hi[0] : lo[0], t2 = n2 ? hi[1] : lo[1];
+    const T t3 = n3 ? hi[2] : lo[2], t4 = n3 ? hi[3] : lo[3];
+    const T q1 = fma_(w.r1b, w.r1b, fma_(w.r1a, w.r1a, fma_(w.s1, w.s1, T(1))));
+    const T q2 = fma_(w.r2b, w.r2b, fma_(w.r2a, w.r2a, fma_(w.s2, w.s2, T(1))));
+    T pa1, pa2, pa3, pa4;
+    if constexpr (sizeof(T) == 8) {
+        const T ip = rcp(q1 * q2);
+        pa1 = mc_scaled(w.a1, t1 * (ip * q2));
+        pa2 = mc_scaled(w.a2, t2 * (ip * q1));
+        pa3 = mc_scaled(w.a3, t3);
+        pa4 = mc_scaled(w.a4, t4);
+    } else {
+        pa1 = mc_half(t1 * rcp(w.a1 * q1)) * w.a1;
+        pa2 = mc_half(t2 * rcp(w.a2 * q2)) * w.a2;
+        pa3 = mc_half(t3 * rcp(w.a3)) * w.a3;
+        pa4 = mc_half(t4 * rcp(w.a4)) * w.a4;
+    }
     const T as1 = abs_(w.s1), as2 = abs_(w.s2), as3 = abs_(w.s3);
     const T f1 = fma_(-dt, as1, T(1)) * as1, f2 = fma_(-dt, as2, T(1)) * as2, f3 = fma_(-dt, as3, T(1)) * as3;
-    const T c1 = f1 * (ps1 * w.a1), c2 = f2 * (ps2 * w.a2), c3 = f3 * (ps3 * w.a3), c4 = f3 * (ps4 * w.a4);
+    const T c1 = f1 * pa1, c2 = f2 * pa2, c3 = f3 * pa3, c4 = f3 * pa4;
     const T m3 = min_(w.s3, T(0));
     const T e1 = fma_(min_(w.s1, T(0)), w.a1, c1);
     const T e2 = fma_(min_(w.s2, T(0)), w.a2, c2);
@@ -174,7 +187,7 @@ __device__ __forceinline__ void hr_split4(const W4<T>& w, const T lo[4], const T
 template <typename T> struct March4 {
     Q4<T> q; T un, ua, ub;     // last cell pushed and its velocities
     W4<T> w;                   // interface below it
-    T lo[4];                   // products of that interface with the one below it, and its alpha^3, alpha^4
+    T lo[4];                   // upwind values t of the interface below it for it (cross4)
     Q4<T> part;                // previous cell minus dt Gp of its lower interface (awaiting its upper flux)
 };
 
@@ -202,10 +215,8 @@ __device__ __forceinline__ void march_push(const Q4<T>& q, const March4<T>& in, 
     T D;
     const T spd = roe4(in.q, in.un, in.ua, in.ub, q, un, ua, ub, beta, wA, D);
     if (count) acc.add(spd, D);
-    T hi[4];
-    dots4(in.w, wA, hi);
-    hi[2] = wA.a3;
-    hi[3] = wA.a4;
+    T tup[4], hi[4];
+    cross4(in.w, wA, tup, hi);
     T Gm[4], Gp[4];
     hr_split4(in.w, in.lo, hi, dt, Gm, Gp);
     done.R = fma_(-dt, Gm[0], in.part.R);
@@ -219,10 +230,10 @@ __device__ __forceinline__ void march_push(const Q4<T>& q, const March4<T>& in, 
     out.q = q;
     out.un = un; out.ua = ua; out.ub = ub;
     out.w = wA;
-    out.lo[0] = hi[0];
-    out.lo[1] = hi[1];
-    out.lo[2] = in.w.a3;
-    out.lo[3] = in.w.a4;
+    out.lo[0] = tup[0];
+    out.lo[1] = tup[1];
+    out.lo[2] = tup[2];
+    out.lo[3] = tup[3];
 }
 
 // Fold a lane's CFL bookkeeping into the clock (one atomic per wavefront).
@@ -307,11 +318,11 @@ void k3_sweep12(Desc3 d, int force)
         W4<T> wr;
         wr.a1 = from_hi(w.a1); wr.s1 = from_hi(w.s1); wr.r1a = from_hi(w.r1a); wr.r1b = from_hi(w.r1b);
         wr.a2 = from_hi(w.a2); wr.s2 = from_hi(w.s2); wr.r2a = from_hi(w.r2a); wr.r2b = from_hi(w.r2b);
-        T hi[4], lo[4];
-        dots4(w, wr, hi);
-        hi[2] = from_hi(w.a3);
-        hi[3] = from_hi(w.a4);
-        lo[0] = from_lo(hi[0]); lo[1] = from_lo(hi[1]); lo[2] = from_lo(w.a3); lo[3] = from_lo(w.a4);
+        wr.a3 = from_hi(w.a3);
+        wr.a4 = from_hi(w.a4);
+        T tup[4], hi[4], lo[4];
+        cross4(w, wr, tup, hi);
+        lo[0] = from_lo(tup[0]); lo[1] = from_lo(tup[1]); lo[2] = from_lo(tup[2]); lo[3] = from_lo(tup[3]);
         T Gm[4], Gp[4];
         hr_split4(w, lo, hi, dt, Gm, Gp);
         Q4<T> o2;

@@ -365,51 +365,59 @@ template <> struct Cfl<double> {
 };
 
 // MC limiter (Sec. 3.1), phi(theta) = max(0, min((1 + theta)/2, 2, 2 theta)),
-// evaluated as psi = phi/2 = max(0, min((1 + theta)/4, 1, theta)).  Halving
-// is exact, and hr_split doubles the factor psi multiplies, so the products
-// round exactly as they would with phi.
-// (1 + theta)/4: FP64 as ldexp(theta + 1, -2) -- 0.25 is not an inline
-// constant of the FP64 instructions, and the compiler rebuilt it in two
-// registers for every call; 1.0 and the exponent are inline, and the scaling
-// is exact, so the value is bitwise that of fma(0.25, theta, 0.25).
-template <typename T>
-__device__ __forceinline__ T quarter_1p(T th)
-{
-    if constexpr (sizeof(T) == 8) return __builtin_ldexp(th + T(1), -2);
-    else return fma_(T(0.25), th, T(0.25));
-}
+// with theta = (W_up . W) / (W . W) for the waves W^p = alpha^p r^p,
+// r^p = (1, s^p, r^p) of families p = 1, 2 and r^3 = (0, 0, 1).  The scheme
+// needs theta only through the product phi(theta) alpha, and only half of it
+// (hr_split doubles the factor it multiplies): psi alpha with psi = phi/2 =
+// max(0, min((1 + theta)/4, 1, theta)).
+//
+// With X = r^p_up . r^p and n = r^p . r^p (>= 1), alpha cancels from the
+// ratio: theta = t / (alpha n), t = alpha_up X.  The neighbour supplies t, so
+// each lane ships t instead of the full product W_up . W.
+//
+// FP32: psi from theta = t / (alpha n), times alpha.  When alpha = 0 the
+// quotient is x/0 or 0/0, psi is then 0 or 1 (min/max return the non-NaN
+// operand), and the product with alpha is 0 -- the value the guard
+// theta := 0 gives.  So no guard is evaluated.
 template <typename T>
 __device__ __forceinline__ T mc_half(T th)
 {
-    return max_(T(0), min_(min_(quarter_1p(th), T(1)), th));
+    return max_(T(0), min_(min_(fma_(T(0.25), th, T(0.25)), T(1)), th));
 }
 
-// Products W^p_a . W^p_b of the waves of two neighbouring interfaces for the
-// families p = 1, 2, with W^p = alpha^p (1, s^p, r^p).  Family 3 has
-// W^3 = (0, 0, alpha^3), so its ratio needs only the neighbour's alpha^3
-// (hr_split), which is what the third entry carries.
-template <typename T>
-__device__ __forceinline__ void wave_dots(const Wave<T>& a, const Wave<T>& b, T d[2])
+// FP64: psi alpha directly from alpha and u = alpha theta = t / n, with no
+// division by alpha.  Scaling the min/max by alpha (and flipping them when
+// alpha < 0) gives, with g the sign of alpha,
+//   psi alpha = g max(0, min((|alpha| + g u)/4, |alpha|, g u)),
+// which is 0 for alpha = 0.  The signs are bit operations on the high word;
+// /4 is exact (ldexp); 1/n is needed for families 1 and 2 only (n = 1 for
+// family 3), and both come from one reciprocal of n1 n2 >= 1 (hr_split).
+// This saves the three reciprocals of alpha^p n^p -- on this chip an FP64
+// reciprocal estimate occupies the SIMD four times as long as an FMA.
+__device__ __forceinline__ double mc_scaled(double a, double u)
 {
-    d[0] = (a.a1 * b.a1) * fma_(a.r1, b.r1, fma_(a.s1, b.s1, T(1)));
-    d[1] = (a.a2 * b.a2) * fma_(a.r2, b.r2, fma_(a.s2, b.s2, T(1)));
+    const unsigned long long g = (unsigned long long)__double_as_longlong(a) & 0x8000000000000000ull;
+    const double gu = __longlong_as_double((long long)((unsigned long long)__double_as_longlong(u) ^ g));
+    const double aa = __builtin_fabs(a);
+    const double m = max_(0.0, min_(min_(__builtin_ldexp(aa + gu, -2), aa), gu));
+    return __longlong_as_double((long long)((unsigned long long)__double_as_longlong(m) | g));
 }
 
-// theta = (W_up . W) / (W . W) (Sec. 3.1).  The paper's method needs theta
-// only through phi(theta) alpha; when W = 0 (alpha = 0) the quotient is 0/0 or
-// x/0, phi is then 0 or 2 (min/max return the non-NaN operand), and the
-// product with alpha = 0 is 0 -- the value the guard theta := 0 gives.  So no
-// guard is evaluated.
+// The upwind values t of two neighbouring interfaces a (below) and b (above)
+// for each other: ta = what b needs when a is its upwind interface (alpha_a X),
+// tb = what a needs when b is upwind (alpha_b X), X = r^p_a . r^p_b for
+// p = 1, 2; entry 2 is the neighbour's alpha^3 (X = 1 for family 3).
 template <typename T>
-__device__ __forceinline__ T theta_of(T dup, T a, T s, T r)
+__device__ __forceinline__ void wave_cross(const Wave<T>& a, const Wave<T>& b, T ta[3], T tb[3])
 {
-    const T den = (a * a) * fma_(r, r, fma_(s, s, T(1)));
-    return dup * rcp(den);
+    const T x1 = fma_(a.r1, b.r1, fma_(a.s1, b.s1, T(1)));
+    const T x2 = fma_(a.r2, b.r2, fma_(a.s2, b.s2, T(1)));
+    ta[0] = a.a1 * x1; ta[1] = a.a2 * x2; ta[2] = a.a3;
+    tb[0] = b.a1 * x1; tb[1] = b.a2 * x2; tb[2] = b.a3;
 }
 
-// From the waves of one interface and the products of its waves with those of
-// the interface below (dlo) and above (dhi) -- entries 0, 1: W^p products of
-// families 1, 2 (wave_dots); entry 2: alpha^3 of that neighbour -- form
+// From the waves of one interface and the upwind values t of the interface
+// below (dlo) and above (dhi) (wave_cross), form
 //   Gm = A^- dQ + F~   (applied to the cell on the low side) and
 //   Gp = A^+ dQ - F~   (applied to the cell on the high side);
 // eqs. fluc:m, fluc:p, limiter, fv-hr.  The upwind interface of family p is
@@ -419,15 +427,28 @@ template <typename T>
 __device__ __forceinline__ void hr_split(const Wave<T>& w, const T dlo[3], const T dhi[3], T dt,
                                          T Gm[3], T Gp[3])
 {
-    const T ps1 = mc_half(theta_of(w.s1 < T(0) ? dhi[0] : dlo[0], w.a1, w.s1, w.r1));
-    const T ps2 = mc_half(theta_of(w.s2 < T(0) ? dhi[1] : dlo[1], w.a2, w.s2, w.r2));
-    // family 3: theta = alpha^3_up alpha^3 / (alpha^3)^2 = alpha^3_up / alpha^3
-    const T ps3 = mc_half((w.s3 < T(0) ? dhi[2] : dlo[2]) * rcp(w.a3));
+    const T t1 = w.s1 < T(0) ? dhi[0] : dlo[0];
+    const T t2 = w.s2 < T(0) ? dhi[1] : dlo[1];
+    const T t3 = w.s3 < T(0) ? dhi[2] : dlo[2];
+    const T n1 = fma_(w.r1, w.r1, fma_(w.s1, w.s1, T(1)));
+    const T n2 = fma_(w.r2, w.r2, fma_(w.s2, w.s2, T(1)));
+    // pa_p = psi^p alpha^p
+    T pa1, pa2, pa3;
+    if constexpr (sizeof(T) == 8) {
+        const T ip = rcp(n1 * n2);
+        pa1 = mc_scaled(w.a1, t1 * (ip * n2));
+        pa2 = mc_scaled(w.a2, t2 * (ip * n1));
+        pa3 = mc_scaled(w.a3, t3);
+    } else {
+        pa1 = mc_half(t1 * rcp(w.a1 * n1)) * w.a1;
+        pa2 = mc_half(t2 * rcp(w.a2 * n2)) * w.a2;
+        pa3 = mc_half(t3 * rcp(w.a3)) * w.a3;
+    }
     const T as1 = abs_(w.s1), as2 = abs_(w.s2), as3 = abs_(w.s3);
     // correction strengths c_p = 1/2 |s| (1 - dt |s|) phi alpha = |s| (1 - dt |s|) psi alpha
-    const T c1 = (fma_(-dt, as1, T(1)) * as1) * (ps1 * w.a1);
-    const T c2 = (fma_(-dt, as2, T(1)) * as2) * (ps2 * w.a2);
-    const T c3 = (fma_(-dt, as3, T(1)) * as3) * (ps3 * w.a3);
+    const T c1 = (fma_(-dt, as1, T(1)) * as1) * pa1;
+    const T c2 = (fma_(-dt, as2, T(1)) * as2) * pa2;
+    const T c3 = (fma_(-dt, as3, T(1)) * as3) * pa3;
     // e_p = min(s,0) alpha + c_p ; g_p = max(s,0) alpha - c_p = s alpha - e_p
     const T e1 = fma_(min_(w.s1, T(0)), w.a1, c1);
     const T e2 = fma_(min_(w.s2, T(0)), w.a2, c2);
@@ -617,7 +638,7 @@ __device__ __forceinline__ void seg_bounds(const SimDesc& d, int seg, int& r0, i
 template <typename T> struct Carry {
     Cell<T> q; T u, v;      // last x1-swept row Q*_v pushed, and its velocities
     Wave<T> w;              // x2 interface v - 1/2
-    T dlo[3];               // W_{v-3/2} . W_{v-1/2} (families 1, 2) and alpha^3_{v-3/2}
+    T dlo[3];               // upwind values t of x2 interface v-3/2 for v-1/2 (wave_cross)
     Cell<T> part;           // Q*_{v-1} - dt Gp_{v-3/2}: row v-1 awaiting its upper flux
     Cell<T> qs; T us, vs;   // x2-swept row v-2 awaiting its source, and its velocities
     T ub, vb;               // velocities of x2-swept row v-3
@@ -800,10 +821,9 @@ __device__ __forceinline__ void march(const SimDesc& d, int strip, int seg)
         wr.a1 = from_hi(w.a1); wr.s1 = from_hi(w.s1); wr.r1 = from_hi(w.r1);
         wr.a2 = from_hi(w.a2); wr.s2 = from_hi(w.s2); wr.r2 = from_hi(w.r2);
         wr.a3 = from_hi(w.a3);
-        T dhi[3], dlo[3];
-        wave_dots(w, wr, dhi);
-        dhi[2] = wr.a3;
-        dlo[0] = from_lo(dhi[0]); dlo[1] = from_lo(dhi[1]); dlo[2] = from_lo(w.a3);
+        T tup[3], dhi[3], dlo[3];
+        wave_cross(w, wr, tup, dhi);
+        dlo[0] = from_lo(tup[0]); dlo[1] = from_lo(tup[1]); dlo[2] = from_lo(tup[2]);
         T Gm[3], Gp[3];
         hr_split(w, dlo, dhi, dt, Gm, Gp);
         const T g0 = from_hi(Gm[0]), g1 = from_hi(Gm[1]), g2 = from_hi(Gm[2]);
@@ -850,9 +870,8 @@ __device__ __forceinline__ void march(const SimDesc& d, int strip, int seg)
         T D;
         const T spd = roe(in.q.R, in.q.N, in.q.M, in.v, in.u, q.R, q.N, q.M, vv, u, beta, wA, D);
         if (LEAN || (v > vfirst && (pery || (v >= 0 && v <= ny)))) yacc.add(spd, D);
-        T dhi[3];
-        wave_dots(in.w, wA, dhi);
-        dhi[2] = wA.a3;
+        T tup[3], dhi[3];
+        wave_cross(in.w, wA, tup, dhi);
         // limited correction and fluctuations at v-3/2
         T Gm[3], Gp[3];
         hr_split(in.w, in.dlo, dhi, dt, Gm, Gp);
@@ -939,7 +958,7 @@ __device__ __forceinline__ void march(const SimDesc& d, int strip, int seg)
         }
         out.q = q; out.u = u; out.v = vv;
         out.w = wA;
-        out.dlo[0] = dhi[0]; out.dlo[1] = dhi[1]; out.dlo[2] = in.w.a3;
+        out.dlo[0] = tup[0]; out.dlo[1] = tup[1]; out.dlo[2] = tup[2];
         out.qs = qn; out.us = un; out.vs = vn;
         out.ub = in.us; out.vb = in.vs;
     };

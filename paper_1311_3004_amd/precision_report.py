@@ -5,7 +5,8 @@ JSON line per precision: throughput (including the sampling of the final
 cycles), the focal peak pressures p+ / p- and harmonics 1..5 at the focal
 cell over the final 5 cycles, the shock-front position (steepest on-axis
 compression near the focus), and the relative errors of each against the FP64
-run.  FP16/BF16 store perturbations scaled by 64 times the source amplitude,
+run, with the front's phase lag by least-squares alignment of the axial
+profiles (diagnostics.front_shift).  FP16/BF16 store perturbations scaled by 64 times the source amplitude,
 so the expected peak is below 1.
 
     python -m paper_1311_3004_amd.precision_report c3      # 8192 x 2048, 0.2 MPa, 20000 steps
@@ -73,10 +74,11 @@ def main(argv):
                "p_plus": summ["p_plus"], "p_minus": summ["p_minus"],
                "harmonics": [float(x) for x in summ["harmonics"]], "front_cells": front, "n_samples": len(t)}
         if ref is None:
-            ref = dict(summ, front=front)
+            ref = dict(summ, front=front, row=row)
         else:
             out.update(dg.compare(summ, ref))
             out["front_err_cells"] = front - ref["front"]
+            out["front_lag_cells"] = dg.front_shift(row, ref["row"], int(round(ref["front"])))
             out["axis_pplus_max_rel"] = float(np.max(np.abs(summ["p_plus_axis"] - ref["p_plus_axis"]))
                                               / np.max(ref["p_plus_axis"]))
         print(json.dumps(out), flush=True)

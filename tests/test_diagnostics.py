@@ -88,3 +88,19 @@ def test_packet_workload_geometry():
     assert abs(wm["source"]["stage2_time"] * f - 12.0) < 1e-12 and wm["window"]["t1"] == wm["source"]["stage2_time"]
     assert wm["window"]["quantum"] == wm["window"]["check_every"] == 10
     assert abs(wf["t0"] * f + 6.0) < 1e-12 and abs(wf["t_end"] * f - 66.5) < 1e-12
+
+
+def test_front_shift_measures_a_known_lag_and_ignores_storage_rounding():
+    """front_shift on a steepened front (a tanh profile 1.5 cells wide) moved
+    by known sub-cell and whole-cell amounts recovers the move to 0.005 cells
+    (the bias of linear interpolation on the sampled reference); rounded to
+    an 11-bit significand (FP16 storage) it still does to 0.02; a lag beyond
+    the scan is reported as None."""
+    z = np.arange(3000.0)
+    prof = lambda s: 2e6 * np.tanh((1500.0 + s - z) / 1.5) + 1e6 * np.exp(-((z - 1480.0 - s) / 30.0) ** 2)
+    ref = prof(0.0)
+    for s in (0.37, -1.23, 2.5, 0.0):
+        assert abs(dg.front_shift(prof(s), ref, 1500) - s) <= 5e-3
+        q = np.float16(prof(s) / 4e6).astype(np.float64) * 4e6
+        assert abs(dg.front_shift(q, ref, 1500) - s) <= 2e-2
+    assert dg.front_shift(prof(12.0), ref, 1500, max_shift=8.0) is None
