@@ -276,17 +276,16 @@ template <typename T> struct Wave { T s1, s2, s3, a1, a2, a3, r1, r2; };
 // excess (so ~1e-10 on the speed itself) -- and the discriminant D in D.
 // When D is not a positive finite number the returned value is meaningless
 // (FP32: always NaN); Cfl::add sorts these cases out.
+// roe_sh takes Sr = RL + RR and h = 1/(2 + Sr) from the caller (rcp_pair).
 template <typename T>
-__device__ __forceinline__ T roe(T RL, T nL, T tL, T vnL, T vtL,
-                                 T RR, T nR, T tR, T vnR, T vtR, T beta, Wave<T>& w, T& D)
+__device__ __forceinline__ T roe_sh(T RL, T nL, T tL, T vnL, T vtL,
+                                    T RR, T nR, T tR, T vnR, T vtR, T beta, T Sr, T h, Wave<T>& w, T& D)
 {
     // Sums of the two sides stand for the means (Zbar^1 - 1 = Sr/2, zn = Sn/2,
     // zt = St/2); every factor of 2 they introduce cancels exactly.
-    const T Sr = RL + RR;
     const T Sn = vnL + vnR;
     const T St = vtL + vtR;
-    const T h = rcp(T(2) + Sr);                   // 1 / (2 Zbar^1)
-    const T wv = Sn * h;                          // w = zn / Zbar^1
+    const T wv = Sn * h;                          // w = zn / Zbar^1, h = 1 / (2 Zbar^1)
     const T D1 = fma_(wv, wv - Sn, (beta - T(1)) * Sr);   // D - 1
     D = T(1) + D1;                                // w^2 - 2 zn^2/Zbar^1 + Phi
     T c, ic;
@@ -305,6 +304,31 @@ __device__ __forceinline__ T roe(T RL, T nL, T tL, T vnL, T vtL,
     w.a2 = d1 - w.a1;
     w.a3 = fma_(-w.a2, w.r2, fma_(-w.a1, w.r1, d3));
     return spd;
+}
+template <typename T>
+__device__ __forceinline__ T roe(T RL, T nL, T tL, T vnL, T vtL,
+                                 T RR, T nR, T tR, T vnR, T vtR, T beta, Wave<T>& w, T& D)
+{
+    const T Sr = RL + RR;
+    return roe_sh(RL, nL, tL, vnL, vtL, RR, nR, tR, vnR, vtR, beta, Sr, rcp(T(2) + Sr), w, D);
+}
+
+// 1/a and 1/b for the two positive factors a = 1 + R of a cell and
+// b = 2 + Sr of an interface it borders: FP64 from one reciprocal of a b
+// (rounding of the product and the two multiplies aside, the same values; a
+// reciprocal estimate holds the SIMD four times as long as an FMA), FP32 two
+// estimates.
+template <typename T>
+__device__ __forceinline__ void rcp_pair(T a, T b, T& ia, T& ib)
+{
+    if constexpr (sizeof(T) == 8) {
+        const T r = rcp(a * b);
+        ia = r * b;
+        ib = r * a;
+    } else {
+        ia = rcp(a);
+        ib = rcp(b);
+    }
 }
 
 // Value the CFL reduction starts from (no interface counted yet) and the
@@ -396,11 +420,10 @@ __device__ __forceinline__ T mc_half(T th)
 // reciprocal estimate occupies the SIMD four times as long as an FMA.
 __device__ __forceinline__ double mc_scaled(double a, double u)
 {
-    const unsigned long long g = (unsigned long long)__double_as_longlong(a) & 0x8000000000000000ull;
-    const double gu = __longlong_as_double((long long)((unsigned long long)__double_as_longlong(u) ^ g));
+    const double gu = u * __builtin_copysign(1.0, a);
     const double aa = __builtin_fabs(a);
     const double m = max_(0.0, min_(min_(__builtin_ldexp(aa + gu, -2), aa), gu));
-    return __longlong_as_double((long long)((unsigned long long)__double_as_longlong(m) | g));
+    return __builtin_copysign(m, a);
 }
 
 // The upwind values t of two neighbouring interfaces a (below) and b (above)
@@ -807,13 +830,16 @@ __device__ __forceinline__ void march(const SimDesc& d, int strip, int seg)
                 if (row_ok && vr + 0.5 <= src_clk.ap) source_at<T>(d, vr, src_clk, q.R, q.M, q.N);
             }
         }
-        const T irho = rcp(T(1) + q.R);
+        const T RL = from_lo(q.R);
+        const T Sr = RL + q.R;
+        T irho, h;
+        rcp_pair(T(1) + q.R, T(2) + Sr, irho, h);
         const T u = q.M * irho, v = q.N * irho;
-        const T RL = from_lo(q.R), ML = from_lo(q.M), NL = from_lo(q.N);
+        const T ML = from_lo(q.M), NL = from_lo(q.N);
         const T uL = from_lo(u), vL = from_lo(v);
         Wave<T> w;
         T D;
-        const T spd = roe(RL, ML, NL, uL, vL, q.R, q.M, q.N, u, v, beta, w, D);
+        const T spd = roe_sh(RL, ML, NL, uL, vL, q.R, q.M, q.N, u, v, beta, Sr, h, w, D);
         if constexpr (!GHOST) xacc.add(spd, D);
         // waves of the interface to the right -> products with it; the lane
         // to the left supplies the products with the interface below
@@ -863,12 +889,14 @@ __device__ __forceinline__ void march(const SimDesc& d, int strip, int seg)
     // ---- push x1-swept row v through the x2 sweep and the source ----
     // src (lean path): whether row v - 3 is an output row of this tile.
     auto push = [&](const Cell<T>& q, int v, const Carry<T>& in, Carry<T>& out, auto src) {
-        const T irho = rcp(T(1) + q.R);
+        const T Sr = in.q.R + q.R;
+        T irho, h;
+        rcp_pair(T(1) + q.R, T(2) + Sr, irho, h);
         const T u = q.M * irho, vv = q.N * irho;
         // x2 interface v-1/2 between rows v-1 (low) and v (high); normal = N
         Wave<T> wA;
         T D;
-        const T spd = roe(in.q.R, in.q.N, in.q.M, in.v, in.u, q.R, q.N, q.M, vv, u, beta, wA, D);
+        const T spd = roe_sh(in.q.R, in.q.N, in.q.M, in.v, in.u, q.R, q.N, q.M, vv, u, beta, Sr, h, wA, D);
         if (LEAN || (v > vfirst && (pery || (v >= 0 && v <= ny)))) yacc.add(spd, D);
         T tup[3], dhi[3];
         wave_cross(in.w, wA, tup, dhi);
