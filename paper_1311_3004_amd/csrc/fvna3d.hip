@@ -87,12 +87,12 @@ template <typename T> struct Q4 { T R, n, a, b; };
 // The means are carried as sums of the two sides (every factor 2 cancels).
 // Returns the interface's largest |s| in the form Cfl<T> reduces (FP32 as an
 // excess over 1) and the discriminant in D.
+// h = 1/(2 + L.R + R.R) comes from the caller (rcp_pair).
 template <typename T>
 __device__ __forceinline__ T roe4(const Q4<T>& L, T unL, T uaL, T ubL, const Q4<T>& R, T unR, T uaR, T ubR,
-                                  T beta, W4<T>& w, T& D)
+                                  T beta, T h, W4<T>& w, T& D)
 {
     const T Sr = L.R + R.R, Sn = unL + unR, Sa = uaL + uaR, Sb = ubL + ubR;
-    const T h = rcp(T(2) + Sr);
     const T wv = Sn * h;
     const T D1 = fma_(wv, wv - Sn, (beta - T(1)) * Sr);
     D = T(1) + D1;
@@ -209,11 +209,12 @@ template <typename T>
 __device__ __forceinline__ void march_push(const Q4<T>& q, const March4<T>& in, March4<T>& out, T beta, T dt,
                                            bool count, Cfl<T>& acc, Q4<T>& done)
 {
-    const T ir = rcp(T(1) + q.R);
+    T ir, h;
+    rcp_pair(T(1) + q.R, T(2) + (in.q.R + q.R), ir, h);
     const T un = q.n * ir, ua = q.a * ir, ub = q.b * ir;
     W4<T> wA;
     T D;
-    const T spd = roe4(in.q, in.un, in.ua, in.ub, q, un, ua, ub, beta, wA, D);
+    const T spd = roe4(in.q, in.un, in.ua, in.ub, q, un, ua, ub, beta, h, wA, D);
     if (count) acc.add(spd, D);
     T tup[4], hi[4];
     cross4(in.w, wA, tup, hi);
@@ -306,14 +307,16 @@ void k3_sweep12(Desc3 d, int force)
     };
     auto xsweep = [&](Q4<T> q) -> Q4<T> {
         q.n = xs * q.n;
-        const T ir = rcp(T(1) + q.R);
-        const T un = q.n * ir, ua = q.a * ir, ub = q.b * ir;
         Q4<T> L;
-        L.R = from_lo(q.R); L.n = from_lo(q.n); L.a = from_lo(q.a); L.b = from_lo(q.b);
+        L.R = from_lo(q.R);
+        T ir, h;
+        rcp_pair(T(1) + q.R, T(2) + (L.R + q.R), ir, h);
+        const T un = q.n * ir, ua = q.a * ir, ub = q.b * ir;
+        L.n = from_lo(q.n); L.a = from_lo(q.a); L.b = from_lo(q.b);
         const T unL = from_lo(un), uaL = from_lo(ua), ubL = from_lo(ub);
         W4<T> w;
         T D;
-        const T spd = roe4(L, unL, uaL, ubL, q, un, ua, ub, beta, w, D);
+        const T spd = roe4(L, unL, uaL, ubL, q, un, ua, ub, beta, h, w, D);
         xacc.add(spd, D);
         W4<T> wr;
         wr.a1 = from_hi(w.a1); wr.s1 = from_hi(w.s1); wr.r1a = from_hi(w.r1a); wr.r1b = from_hi(w.r1b);
