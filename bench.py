@@ -44,19 +44,19 @@ BYTES_PER_CELL = {"f64": 48, "f32": 24, "f32_f16store": 12, "f32_bf16store": 12}
 # after any change they report null until profiled again.
 PMC_SOURCES = ("csrc/fvna_device.hpp", "csrc/fvna_step.hpp", "csrc/fvna_runtime.hip", "build.py")
 _PROFILED = {
-    "csrc/fvna_device.hpp": "74960d76f9a7e80936cb5e8a5ea589f40701c0f20695623219678db13cd6fa7e",
+    "csrc/fvna_device.hpp": "c71a918c1bfee5d864a289c5a652bda997bf643ad36ecba04a2e46fc95437c5d",
     "csrc/fvna_step.hpp": "bdaa87da40e74c672a969a9b5e399e58b6871975b76743ca535f1ce64673c707",
     "csrc/fvna_runtime.hip": "205bfd4382d92ca969af3c5710c773d27af5000d46223750f815c9002ca3b582",
     "build.py": "02eda4061ab4ab18fbd0c2e868524ec4e9acf39f5fa26d0513e48c2fca74259e",
 }
 PMC = {
     # profiles/k_step_f64_gaussian4096.md
-    "k_step<double,double,0>": {"nx": 4096, "ny": 4096, "fetch_bytes": 4.2197e+08, "write_bytes": 4.0467e+08,
-                                "valu_lane_ops_per_cell": 409.8, "valu_issue_cycles_per_cell": 28.42,
+    "k_step<double,double,0>": {"nx": 4096, "ny": 4096, "fetch_bytes": 4.2195e+08, "write_bytes": 4.0521e+08,
+                                "valu_lane_ops_per_cell": 400.0, "valu_issue_cycles_per_cell": 26.51,
                                 "sources": _PROFILED},
     # profiles/k_step_f32_gaussian4096.md
-    "k_step<float,float,0>": {"nx": 4096, "ny": 4096, "fetch_bytes": 2.1632e+08, "write_bytes": 2.0434e+08,
-                              "valu_lane_ops_per_cell": 307.6, "valu_issue_cycles_per_cell": 20.33,
+    "k_step<float,float,0>": {"nx": 4096, "ny": 4096, "fetch_bytes": 2.1633e+08, "write_bytes": 2.0419e+08,
+                              "valu_lane_ops_per_cell": 302.9, "valu_issue_cycles_per_cell": 20.03,
                               "sources": _PROFILED},
 }
 
