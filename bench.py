@@ -176,13 +176,14 @@ def other_configs(fvna, inputs, steps):
     return out
 
 
-def three_d(n=256, steps=200):
+def three_d(n=256, steps=200, precision="f32"):
     """The 3-D step (fused x1-x2 sweep, x3 sweep, source and a device-side
-    controller, replayed from a HIP graph) on an n^3 FP32 Gaussian pulse
-    (sigma 8 cells, 2 MPa, 0.5% noise, seed 5), extrapolating sides: whole
-    steps per second (host clock around fvna3_step, which waits once at its
-    end) and the mean duration of the three kernels of one step (HIP events)
-    against 32 B per cell-update (read and write of four FP32 fields)."""
+    controller, replayed from a HIP graph) on an n^3 Gaussian pulse (sigma 8
+    cells, 2 MPa, 0.5% noise, seed 5), extrapolating sides, in FP32 or FP64:
+    whole steps per second (host clock around fvna3_step, which waits once at
+    its end) and the mean duration of the three kernels of one step (HIP
+    events) against 32 B (FP32) or 64 B (FP64) per cell-update (read and
+    write of four fields)."""
     import time
     import numpy as np
     from paper_1311_3004_amd import fvna3d as f3
@@ -194,7 +195,7 @@ def three_d(n=256, steps=200):
     R = a * np.exp(-(c[:, None, None] + c[None, :, None] + c[None, None, :]) / (2 * 8.0 ** 2))
     R += 0.005 * a * rng.uniform(-1, 1, R.shape)
     Z = np.zeros_like(R)
-    s = f3.Sim3(f3.make_params(n, n, n, 1e-4, med, precision="f32"))
+    s = f3.Sim3(f3.make_params(n, n, n, 1e-4, med, precision=precision))
     s.fvna3_set_state(R * med["rho0"], Z, Z, Z)
     del R, Z
     s.fvna3_step(3)
@@ -203,13 +204,14 @@ def three_d(n=256, steps=200):
     wall = time.perf_counter() - t0
     ms = s.fvna3_time_step_kernels(10)
     cells = n ** 3
-    gbs = 32 * cells / (ms * 1e-3) / 1e9
+    bpc = 32 if precision == "f32" else 64
+    gbs = bpc * cells / (ms * 1e-3) / 1e9
     s.fvna3_destroy()
-    log(f"[bench] 3-D {n}^3 fp32: {cells * steps / wall / 1e6:.1f} Mcell/s, step kernels {ms:.3f} ms = {gbs:.0f} GB/s")
-    return {"workload": f"gaussian-pulse {n}^3 fp32", "value": round(cells * steps / wall / 1e6, 1),
+    log(f"[bench] 3-D {n}^3 {precision}: {cells * steps / wall / 1e6:.1f} Mcell/s, step kernels {ms:.3f} ms = {gbs:.0f} GB/s")
+    return {"workload": f"gaussian-pulse {n}^3 {precision}", "value": round(cells * steps / wall / 1e6, 1),
             "unit": "Mcell-updates/s", "steps": steps, "step_kernels_ms": round(ms, 4),
             "kernel_rate": round(cells / (ms * 1e-3) / 1e6, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
-            "bytes_per_cell_update": 32}
+            "bytes_per_cell_update": bpc}
 
 
 def cpu_model():
@@ -403,6 +405,7 @@ def main():
         extra["other_configs"] = other_configs(fvna, inputs, args.other_steps)
     if not args.fp32_only and not args.no_3d:
         extra["three_d"] = three_d()
+        extra["three_d_f64"] = three_d(precision="f64")
 
     out = {
         "metric": "Mcell-updates/s and % HBM roofline, FP32/batched vs FP64 at stated error",
