@@ -44,6 +44,9 @@ struct Desc3 {
     int n[3];                  // nx, ny, nz
     int pitch;                 // elements per x1 row (padded to 256 bytes)
     int strips12, segs12, rows12;   // x1-x2 tiles: 60-column strips, row segments of rows12
+    int tailw12, tailp12, tailk12;  // packed tail (tailw12 > 0): the last nx mod 60 columns of
+                                    // tailp12 planes per wavefront, lanes in segments of
+                                    // tailw12 = that + 4; tailk12 plane groups
     int strips64, segs3, planes3;   // x3 tiles: 64-column strips, z segments of planes3
     int segs4, planes4;             // source tiles: z segments of planes4 (blocks of four rows)
     long long plane;           // elements per field = pitch * ny * nz
@@ -265,23 +268,53 @@ __device__ __forceinline__ bool step_owed(const Clock* c, int force)
 // r1 + 1 go through the x1 sweep and the x2 march; a row outside the grid is
 // the x1 sweep of the row its side rule names (mirrored rows with M2
 // negated), which is the side rule applied to the x1-swept state.
+//
+// TAIL: the last nx mod 60 columns (rem) would fill a 60-column strip only
+// in part (256 columns: 16 of 60).  Their tiles instead pack tailp12 planes
+// into one wavefront: lane segments of w = rem + 4 lanes, segment s holding
+// columns c0 - 2 .. c0 + rem + 1 of plane kg tailp12 + s.  The lane shifts
+// run across segment ends; what crosses them reaches only the two end lanes
+// of a segment, which are its halo, exactly as at the ends of a full strip.
+// Lanes of no segment or past the last plane read a real cell and store and
+// count nothing.
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occupancy<T>::waves)))
-void k3_sweep12(Desc3 d, int force)
+__device__ __forceinline__ void sweep12_lanes(const Desc3& d, int tile, int& seg, int& k, int& col, int& loc,
+                                              int& w, bool& lane_ok)
 {
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int tile = xcd_block(blockIdx.x, gridDim.x) * WAVES_PER_BLOCK + wave;
-    const int ntiles = d.strips12 * d.segs12 * d.n[2];
-    if (tile >= ntiles) return;
-    const Clock* clk = d.clk;
-    if (!step_owed(clk, force)) return;
-    const int strip = tile % d.strips12;
-    const int seg = (tile / d.strips12) % d.segs12;
-    const int k = tile / (d.strips12 * d.segs12);
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int nfull = d.strips12 * d.segs12 * d.n[2];
+    int c0, k0, np;
+    if (tile < nfull) {
+        const int strip = tile % d.strips12;
+        seg = (tile / d.strips12) % d.segs12;
+        k0 = tile / (d.strips12 * d.segs12);
+        c0 = strip * OUT12;
+        w = WAVE;
+        np = 1;
+    } else {
+        const int t = tile - nfull;
+        seg = t % d.segs12;
+        k0 = (t / d.segs12) * d.tailp12;
+        c0 = d.strips12 * OUT12;
+        w = d.tailw12;
+        np = d.tailp12;
+    }
+    const int sgm = lane / w;
+    loc = lane - sgm * w;
+    const int kk = k0 + sgm;
+    lane_ok = sgm < np && kk < d.n[2];
+    k = lane_ok ? kk : d.n[2] - 1;
+    col = c0 - HALO12 + loc;
+}
+
+template <typename T>
+__device__ __forceinline__ void sweep12_tile(const Desc3& d, int tile, const Clock* clk)
+{
     const int nx = d.n[0], ny = d.n[1];
     const int lane = threadIdx.x & (WAVE - 1);
-    const int col = strip * OUT12 - HALO12 + lane;
+    int seg, k, col, loc, w;
+    bool lane_ok;
+    sweep12_lanes(d, tile, seg, k, col, loc, w, lane_ok);
     const int r0 = seg * d.rows12, r1 = min(r0 + d.rows12, ny);
     const T dt = (T)clk->dt;
     const int cur = clk->cur;
@@ -294,16 +327,20 @@ void k3_sweep12(Desc3 d, int force)
     const T xs = xneg ? T(-1) : T(1);
     const size_t pl = (size_t)d.plane;
     const size_t zoff = (size_t)k * (size_t)ny * (size_t)d.pitch;
-    const bool out_lane = lane >= HALO12 && lane < WAVE - HALO12 && col < nx;
+    const bool out_lane = lane_ok && loc >= HALO12 && loc < w - HALO12 && col < nx;
     Cfl<T> xacc, yacc;
 
     // x1 sweep of stored row sr (lane-parallel), components (R, M1, M2, M3)
     // raw Q^n of the row that row v stands for (side rule along x2)
+    // this lane's plane and column, fixed over the march (the row offset
+    // added per row is the same for every lane)
+    const T* __restrict__ in_l = in + (zoff + (size_t)scol);
+    T* __restrict__ out_l = out + (zoff + (size_t)(out_lane ? col : 0));
     auto load_row = [&](int v) -> Q4<T> {
         bool yneg;
         const int sr = side_map(d, 1, v, yneg);
-        const size_t o = zoff + (size_t)sr * (size_t)d.pitch + (size_t)scol;
-        return Q4<T>{in[o], in[pl + o], in[2 * pl + o], in[3 * pl + o]};
+        const T* q = in_l + (size_t)sr * (size_t)d.pitch;
+        return Q4<T>{q[0], q[pl], q[2 * pl], q[3 * pl]};
     };
     auto xsweep = [&](Q4<T> q) -> Q4<T> {
         q.n = xs * q.n;
@@ -314,20 +351,20 @@ void k3_sweep12(Desc3 d, int force)
         const T un = q.n * ir, ua = q.a * ir, ub = q.b * ir;
         L.n = from_lo(q.n); L.a = from_lo(q.a); L.b = from_lo(q.b);
         const T unL = from_lo(un), uaL = from_lo(ua), ubL = from_lo(ub);
-        W4<T> w;
+        W4<T> wv;
         T D;
-        const T spd = roe4(L, unL, uaL, ubL, q, un, ua, ub, beta, h, w, D);
+        const T spd = roe4(L, unL, uaL, ubL, q, un, ua, ub, beta, h, wv, D);
         xacc.add(spd, D);
         W4<T> wr;
-        wr.a1 = from_hi(w.a1); wr.s1 = from_hi(w.s1); wr.r1a = from_hi(w.r1a); wr.r1b = from_hi(w.r1b);
-        wr.a2 = from_hi(w.a2); wr.s2 = from_hi(w.s2); wr.r2a = from_hi(w.r2a); wr.r2b = from_hi(w.r2b);
-        wr.a3 = from_hi(w.a3);
-        wr.a4 = from_hi(w.a4);
+        wr.a1 = from_hi(wv.a1); wr.s1 = from_hi(wv.s1); wr.r1a = from_hi(wv.r1a); wr.r1b = from_hi(wv.r1b);
+        wr.a2 = from_hi(wv.a2); wr.s2 = from_hi(wv.s2); wr.r2a = from_hi(wv.r2a); wr.r2b = from_hi(wv.r2b);
+        wr.a3 = from_hi(wv.a3);
+        wr.a4 = from_hi(wv.a4);
         T tup[4], hi[4], lo[4];
-        cross4(w, wr, tup, hi);
+        cross4(wv, wr, tup, hi);
         lo[0] = from_lo(tup[0]); lo[1] = from_lo(tup[1]); lo[2] = from_lo(tup[2]); lo[3] = from_lo(tup[3]);
         T Gm[4], Gp[4];
-        hr_split4(w, lo, hi, dt, Gm, Gp);
+        hr_split4(wv, lo, hi, dt, Gm, Gp);
         Q4<T> o2;
         o2.R = fma_(-dt, from_hi(Gm[0]) + Gp[0], q.R);
         o2.n = fma_(-dt, from_hi(Gm[1]) + Gp[1], q.n);
@@ -354,11 +391,11 @@ void k3_sweep12(Desc3 d, int force)
         march_push(q, mi, mo, beta, dt, cnt, yacc, dn);
         const int j = v - 2;
         if (j >= r0 && out_lane) {
-            const size_t o = zoff + (size_t)j * (size_t)d.pitch + (size_t)col;
-            out[o] = dn.R;
-            out[pl + o] = dn.a;
-            out[2 * pl + o] = dn.n;
-            out[3 * pl + o] = dn.b;
+            T* o = out_l + (size_t)j * (size_t)d.pitch;
+            o[0] = dn.R;
+            o[pl] = dn.a;
+            o[2 * pl] = dn.n;
+            o[3 * pl] = dn.b;
         }
     };
     // two rows of loads in flight ahead of the row being swept (rows past
@@ -376,11 +413,12 @@ void k3_sweep12(Desc3 d, int force)
     }
     if (v < v1) step_row(v, p0, A, B);
 
-    // x1 interfaces: lane l's lies between columns col - 1 and col (lane 0
-    // has no left neighbour); x2 interfaces: lanes with exact x1-swept values
+    // x1 interfaces: a lane's lies between columns col - 1 and col (the
+    // first lane of a segment has no left neighbour); x2 interfaces: lanes
+    // with exact x1-swept values
     const bool real_col = perx || (col >= 0 && col < nx);
-    const bool cnt_x = lane >= 1 && (perx || (col >= 0 && col <= nx));
-    const bool cnt_y = lane >= HALO12 && lane < WAVE - HALO12 && real_col;
+    const bool cnt_x = lane_ok && loc >= 1 && (perx || (col >= 0 && col <= nx));
+    const bool cnt_y = lane_ok && loc >= HALO12 && loc < w - HALO12 && real_col;
     T sx, sy;
     bool hx, hy, fx, fy;
     xacc.finish(cnt_x, sx, hx, fx);
@@ -393,6 +431,19 @@ void k3_sweep12(Desc3 d, int force)
         const unsigned fl = (anyh ? FLAG_NONHYP : 0u) | (anyf ? FLAG_NONFINITE : 0u);
         if (fl) atomicOr(&d.clk->flags, fl);
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occupancy<T>::waves)))
+void k3_sweep12(Desc3 d, int force)
+{
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tile = xcd_block(blockIdx.x, gridDim.x) * WAVES_PER_BLOCK + wave;
+    const int nfull = d.strips12 * d.segs12 * d.n[2];
+    if (tile >= nfull + d.tailk12 * d.segs12) return;
+    const Clock* clk = d.clk;
+    if (!step_owed(clk, force)) return;
+    sweep12_tile<T>(d, tile, clk);
 }
 
 // ---------------------------------------------------------------------------
@@ -751,7 +802,7 @@ namespace {
 template <typename T>
 void launch_sweeps(const Desc3& d, int force, hipStream_t s, bool source)
 {
-    const int t12 = d.strips12 * d.segs12 * d.n[2];
+    const int t12 = (d.strips12 * d.n[2] + d.tailk12) * d.segs12;
     const int t3 = d.strips64 * d.n[1] * d.segs3;
     hipLaunchKernelGGL(k3_sweep12<T>, dim3((t12 + 3) / 4), dim3(256), 0, s, d, force);
     hipLaunchKernelGGL(k3_sweep3<T>, dim3((t3 + 3) / 4), dim3(256), 0, s, d, force);
@@ -869,8 +920,38 @@ fvna_status fvna3_create(const fvna3_params* p, void* buf_a, void* buf_b, void* 
 #define FVNA3_WAVES 4
 #endif
     const int waves = p->precision == FVNA_F64 ? 2 : FVNA3_WAVES;
-    d.strips12 = (p->nx + OUT12 - 1) / OUT12;
-    d.rows12 = seg_len((long long)d.strips12 * p->nz, p->ny, cus, waves);
+    // x1-x2 tiles: full 60-column strips, and the remaining nx mod 60
+    // columns packed several planes to a wavefront when at least two fit
+    // (256^3 FP32: 3330 wavefronts instead of 3840)
+    const int rem12 = p->nx % OUT12, tw = rem12 + 2 * HALO12;
+#ifndef FVNA3_PACK_TAIL
+#define FVNA3_PACK_TAIL 1
+#endif
+    if (FVNA3_PACK_TAIL && rem12 > 0 && WAVE / tw >= 2) {
+        d.strips12 = p->nx / OUT12;
+        d.tailw12 = tw;
+        d.tailp12 = WAVE / tw;
+        d.tailk12 = (p->nz + d.tailp12 - 1) / d.tailp12;
+    } else {
+        d.strips12 = (p->nx + OUT12 - 1) / OUT12;
+        d.tailw12 = 0;
+        d.tailp12 = 1;
+        d.tailk12 = 0;
+    }
+    // row segments for about six x1-x2 tiles per SIMD: several rounds of
+    // wavefronts let the dispatcher even out the load of the SIMDs, where
+    // one round leaves some with a wavefront more than others (256^3, per
+    // step: FP32 0.470 ms with one round of 86-row tiles, 0.448 with 43-row
+    // tiles; FP64 0.918 with whole 256-row columns, 0.762 with 43 rows;
+    // 64 / 52 / 37 rows measured 0.459 / 0.453 / 0.450 and 0.769 / 0.773 /
+    // 0.764 ms); never fewer than 16 rows (two warm-up rows at each end)
+    {
+        const long long units = (long long)d.strips12 * p->nz + d.tailk12;
+        const long long want = 6ll * cus * 4;
+        const long long nseg = std::max(1ll, (want + units - 1) / units);
+        d.rows12 = (int)std::max(16ll, std::min((long long)p->ny, ((long long)p->ny + nseg - 1) / nseg));
+        d.rows12 = std::min(d.rows12, p->ny);
+    }
     d.segs12 = (p->ny + d.rows12 - 1) / d.rows12;
     d.strips64 = (p->nx + WAVE - 1) / WAVE;
     d.planes3 = seg_len((long long)d.strips64 * p->ny, p->nz, cus, waves);
