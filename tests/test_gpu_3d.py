@@ -30,14 +30,14 @@ def _state(nx, ny, nz, seed):
     return R, M
 
 
-def _run_pair(precision, steps, fixed, dt_cells=0.6, shape=(20, 14, 10), seed=3):
+def _run_pair(precision, steps, fixed, dt_cells=0.6, shape=(20, 14, 10), seed=3, bc=BC):
     from paper_1311_3004_amd import fvna3d as f3
     from oracle import oracle3d as o3
     nx, ny, nz = shape
     R, M = _state(nx, ny, nz, seed)
     rho0, c0 = MED["rho0"], MED["c0"]
     dt_si = dt_cells * DX / c0 if fixed else 0.0
-    p = f3.make_params(nx, ny, nz, DX, MED, bc=BC, precision=precision, fixed_dt=fixed, dt0=dt_si)
+    p = f3.make_params(nx, ny, nz, DX, MED, bc=bc, precision=precision, fixed_dt=fixed, dt0=dt_si)
     s = f3.Sim3(p)
     s.fvna3_set_state(R * rho0, *[m * rho0 * c0 for m in M])
     s.fvna3_step(steps)
@@ -45,7 +45,7 @@ def _run_pair(precision, steps, fixed, dt_cells=0.6, shape=(20, 14, 10), seed=3)
     st = s.fvna3_get_stats()
     s.fvna3_destroy()
     g = (g[0] / rho0,) + tuple(m / (rho0 * c0) for m in g[1:])
-    po = o3.make_params(nx, ny, nz, MED["beta"], MED["delta"] / (c0 * DX), bc=BC, fixed_dt=fixed)
+    po = o3.make_params(nx, ny, nz, MED["beta"], MED["delta"] / (c0 * DX), bc=bc, fixed_dt=fixed)
     o, info = o3.run(po, [R] + M, steps, dt=dt_cells if fixed else 0.0)
     assert info["status"] == 0 and st["steps"] == steps
     err = max(np.max(np.abs(a - b)) for a, b in zip(g, o)) / np.max(np.abs(o[0]))
@@ -75,6 +75,24 @@ def test_3d_step_vs_oracle_large(precision, fixed, tol):
     if not fixed:
         rel_t = 1e-12 if precision == "f64" else 1e-7
         assert abs(st["t"] * MED["c0"] / DX - info["t"]) <= rel_t * info["t"]
+
+
+BC_PERIODIC_X = ("periodic", "periodic", "reflect", "extrap0", "periodic", "periodic")
+
+
+@pytest.mark.parametrize("shape", [(76, 18, 7), (140, 12, 7)])
+@pytest.mark.parametrize("precision,fixed,tol", [("f64", True, 1e-12), ("f32", False, 2e-6)])
+def test_3d_packed_tail_vs_oracle(shape, precision, fixed, tol):
+    """The x1-x2 sweep's packed tail: the last nx mod 60 columns (16 and 20)
+    of three and two planes per wavefront, 7 planes so that the last tail
+    wavefront has idle segments, periodic x1 (the tail's right halo wraps to
+    the first columns) and x3, reflecting / extrapolating x2."""
+    _say(f"case: 3-D packed tail {shape} {precision} {'fixed' if fixed else 'adaptive'} dt, 8 steps")
+    err, st, info = _run_pair(precision, 8, fixed, shape=shape, seed=7, bc=BC_PERIODIC_X)
+    _say(f"  max rel err {err:.3e}")
+    assert err <= tol
+    if not fixed:
+        assert abs(st["t"] * MED["c0"] / DX - info["t"]) <= 1e-7 * info["t"]
 
 
 def test_3d_refuses_bad_parameters():
