@@ -521,10 +521,11 @@ __global__ __launch_bounds__(256) void k3_sweep3(Desc3 d, int force)
 
 // ---------------------------------------------------------------------------
 // Source (3-D form of eq. fs:source, forward Euler): M_c += dt delta~ lap(u_c),
-// 7-point Laplacian of u_c = M_c / (1 + R), R unchanged.  A block of four
-// wavefronts takes rows 4g .. 4g + 3 of one 64-column strip over planes
-// k0 .. k1 - 1: lane = column, wave = row.  Per plane each wave publishes its
-// row's velocities in LDS (waves 0 and 3 also the rows 4g - 1 and 4g + 4),
+// 7-point Laplacian of u_c = M_c / (1 + R), R unchanged.  A block of
+// SRC_ROWS (= s) wavefronts takes rows s g .. s g + s - 1 of one 64-column
+// strip over planes k0 .. k1 - 1: lane = column, wave = row.  Per plane each
+// wave publishes its row's velocities in LDS (the first and last waves also
+// the rows s g - 1 and s g + s),
 // and after one barrier reads its x2 neighbours there; x3 neighbours are
 // carried in registers, x1 neighbours come over DPP (the strip's end lanes
 // load theirs).  Neighbours outside the grid follow the side rules (mirrored
@@ -534,11 +535,20 @@ __global__ __launch_bounds__(256) void k3_sweep3(Desc3 d, int force)
 // ---------------------------------------------------------------------------
 template <typename T> struct Vel { T u1, u2, u3; };
 
+// Rows (wavefronts) per source block.  Eight rows read fewer halo rows (10
+// per 8 instead of 6 per 4) but measured level: 256^3 per step FP32 0.451 ms
+// with 4 or 8, FP64 0.783 / 0.775 ms.
+#ifndef FVNA3_SRC_ROWS
+#define FVNA3_SRC_ROWS 4
+#endif
+constexpr int SRC_ROWS = FVNA3_SRC_ROWS;
+
 template <typename T>
-__global__ __launch_bounds__(256) void k3_source(Desc3 d, int force)
+__global__ __launch_bounds__(WAVE * SRC_ROWS) void k3_source(Desc3 d, int force)
 {
-    __shared__ T ys[2][6][3][WAVE];                 // [plane parity][row 4g-1 .. 4g+4][component][lane]
-    const int ngroups = (d.n[1] + 3) / 4;
+    // [plane parity][row g SRC_ROWS - 1 .. (g + 1) SRC_ROWS][component][lane]
+    __shared__ T ys[2][SRC_ROWS + 2][3][WAVE];
+    const int ngroups = (d.n[1] + SRC_ROWS - 1) / SRC_ROWS;
     const int b = xcd_block(blockIdx.x, gridDim.x);
     if (b >= d.strips64 * ngroups * d.segs4) return;        // the whole block
     const Clock* clk = d.clk;
@@ -550,7 +560,7 @@ __global__ __launch_bounds__(256) void k3_source(Desc3 d, int force)
     const int nx = d.n[0], ny = d.n[1], nz = d.n[2];
     const int lane = threadIdx.x & (WAVE - 1);
     const int col = strip * WAVE + lane;
-    const int j = 4 * g + wave;
+    const int j = SRC_ROWS * g + wave;
     // lanes past the last column hold the x+ ghost by the side rule (the
     // lane after the last column is that column's right neighbour); rows past
     // the last row likewise hold the y+ ghost
@@ -571,10 +581,10 @@ __global__ __launch_bounds__(256) void k3_source(Desc3 d, int force)
     if (lane == 0) ecol = side_map(d, 0, col - 1, eneg);
     else if (lane == WAVE - 1) ecol = side_map(d, 0, col + 1, eneg);
     // halo rows: wave 0 publishes row 4g - 1, wave 3 row 4g + 4
-    const bool halo = wave == 0 || wave == 3;
+    const bool halo = wave == 0 || wave == SRC_ROWS - 1;
     bool hneg = false;
-    const int hj = halo ? side_map(d, 1, wave == 0 ? 4 * g - 1 : 4 * g + 4, hneg) : sj;
-    const int hslot = wave == 0 ? 0 : 5;
+    const int hj = halo ? side_map(d, 1, wave == 0 ? SRC_ROWS * g - 1 : SRC_ROWS * (g + 1), hneg) : sj;
+    const int hslot = wave == 0 ? 0 : SRC_ROWS + 1;
     // raw cell at element offset o with the mirrored components negated
     auto raw = [&](size_t o, bool neg1, bool neg2, bool neg3) -> Q4<T> {
         Q4<T> q{in[o], in[pl + o], in[2 * pl + o], in[3 * pl + o]};
@@ -806,8 +816,8 @@ void launch_sweeps(const Desc3& d, int force, hipStream_t s, bool source)
     const int t3 = d.strips64 * d.n[1] * d.segs3;
     hipLaunchKernelGGL(k3_sweep12<T>, dim3((t12 + 3) / 4), dim3(256), 0, s, d, force);
     hipLaunchKernelGGL(k3_sweep3<T>, dim3((t3 + 3) / 4), dim3(256), 0, s, d, force);
-    const int tsrc = d.strips64 * ((d.n[1] + 3) / 4) * d.segs4;    // blocks of four rows
-    if (source) hipLaunchKernelGGL(k3_source<T>, dim3(tsrc), dim3(256), 0, s, d, force);
+    const int tsrc = d.strips64 * ((d.n[1] + SRC_ROWS - 1) / SRC_ROWS) * d.segs4;    // blocks of SRC_ROWS rows
+    if (source) hipLaunchKernelGGL(k3_source<T>, dim3(tsrc), dim3(WAVE * SRC_ROWS), 0, s, d, force);
 }
 
 template <typename T>
