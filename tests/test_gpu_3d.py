@@ -122,3 +122,53 @@ def test_3d_reports_a_nonhyperbolic_state():
     s.fvna3_step(3)
     assert s.fvna3_get_stats()["steps"] == 3
     s.fvna3_destroy()
+
+
+@pytest.fixture(scope="module")
+def bench3d_oracle():
+    """The 3-D benchmark workload (256^3 Gaussian pulse, sigma 8 cells, 2 MPa,
+    0.5% noise with seed 5, water, extrapolating sides) and one fixed-dt step
+    of the FP64 oracle on it (about 20 s on one host core)."""
+    from oracle import oracle3d as o3
+    from paper_1311_3004_amd.inputs import WATER
+    n = 256
+    med = dict(WATER)
+    rng = np.random.default_rng(5)
+    c = (np.arange(n) + 0.5 - n / 2) ** 2
+    a = 2e6 / (med["rho0"] * med["c0"] ** 2)
+    R = a * np.exp(-(c[:, None, None] + c[None, :, None] + c[None, None, :]) / (2 * 8.0 ** 2))
+    R += 0.005 * a * rng.uniform(-1, 1, R.shape)
+    Z = np.zeros_like(R)
+    _say("case: 3-D 256^3 benchmark workload, oracle FP64, 1 fixed-dt step")
+    po = o3.make_params(n, n, n, med["beta"], med["delta"] / (med["c0"] * 1e-4), bc=("extrap0",) * 6,
+                        fixed_dt=True)
+    o, info = o3.run(po, [R, Z, Z, Z], 1, dt=0.6)
+    assert info["status"] == 0
+    return med, R, o
+
+
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-12), ("f32", 2e-6)])
+def test_3d_benchmark_size_one_step_vs_oracle(bench3d_oracle, precision, tol):
+    """The 256^3 workload bench.py times, in the launch plan it times (four
+    60-column strips and a three-plane packed tail, 43-row segments over
+    several rounds, the x3 sweep and the source in one round of z-segments):
+    one fixed-dt step, every cell against the oracle."""
+    from paper_1311_3004_amd import fvna3d as f3
+    med, R, o = bench3d_oracle
+    n = R.shape[0]
+    rho0, c0 = med["rho0"], med["c0"]
+    _say(f"case: 3-D 256^3 benchmark workload {precision}, 1 fixed-dt step")
+    p = f3.make_params(n, n, n, 1e-4, med, bc=("extrap0",) * 6, precision=precision, fixed_dt=True,
+                       dt0=0.6 * 1e-4 / c0)
+    s = f3.Sim3(p)
+    Z = np.zeros_like(R)
+    s.fvna3_set_state(R * rho0, Z, Z, Z)
+    s.fvna3_step(1)
+    g = s.fvna3_get_state()
+    st = s.fvna3_get_stats()
+    s.fvna3_destroy()
+    assert st["steps"] == 1 and st["status"] == 0
+    g = (g[0] / rho0,) + tuple(m / (rho0 * c0) for m in g[1:])
+    err = max(np.max(np.abs(a - b)) for a, b in zip(g, o)) / np.max(np.abs(o[0]))
+    _say(f"  max rel err {err:.3e}")
+    assert err <= tol
