@@ -197,15 +197,17 @@ def _focal(w, res, prec, zstar=None):
 # diagnostics.front_shift); None: the precision does not resolve that quantity
 # and no bound is claimed.  FP16 storage resolves the focal pressures, the
 # first three harmonics and the front; BF16 (8-bit significand) only the focal
-# pressures, to about 1% -- its harmonics are off by 12-280% and its front by
-# more than 3 cells.  Half-width storage rounds every cell of every step, so
-# these errors move with rounding-level changes of the FP32 arithmetic (two
-# builds that differ only there: BF16 p+ 2.7e-3 and 7.8e-3, p- 1.1e-3 and
-# 9.3e-3); the bounds hold for both.
+# pressures, to about 2% -- its harmonics are off by 12-280% and its front by
+# 2-8 cells.  Half-width storage rounds every cell of every step, so these
+# errors move with rounding-level changes: of the FP32 arithmetic (two builds
+# that differ only there: BF16 p+ 2.7e-3 and 7.8e-3, p- 1.1e-3 and 9.3e-3) and
+# of the storage scale (56 a ... 72 a: FP16 p+/- <= 3.0e-3, harmonics 1-3 <=
+# 1.4e-3 / 5.4e-3 / 2.0e-2, lag <= 0.08 cells; BF16 p+/- 1.1e-3 ... 1.8e-2);
+# the bounds hold for all of them.
 @pytest.mark.parametrize("prec,tol_peak,tol_h,tol_front", [
     ("f32", 1e-4, [1e-4, 1e-3, 1e-3, 1e-3, 5e-3], 0.05),
     ("f32_f16store", 5e-3, [5e-3, 1e-2, 3e-2, None, None], 0.5),
-    ("f32_bf16store", 1.5e-2, [None] * 5, None),
+    ("f32_bf16store", 2.5e-2, [None] * 5, None),
 ])
 def test_hifu_axisym_precisions_against_fp64(hifu_runs, prec, tol_peak, tol_h, tol_front):
     from paper_1311_3004_amd import diagnostics as dg
