@@ -44,7 +44,7 @@ BYTES_PER_CELL = {"f64": 48, "f32": 24, "f32_f16store": 12, "f32_bf16store": 12}
 # after any change they report null until profiled again.
 PMC_SOURCES = ("csrc/fvna_device.hpp", "csrc/fvna_step.hpp", "csrc/fvna_runtime.hip", "build.py")
 _PROFILED = {
-    "csrc/fvna_device.hpp": "c71a918c1bfee5d864a289c5a652bda997bf643ad36ecba04a2e46fc95437c5d",
+    "csrc/fvna_device.hpp": "c729c2c4f4e3c897eadd7999c90205e4af7dba1c2c9c84628fc1c021f17fa238",
     "csrc/fvna_step.hpp": "bdaa87da40e74c672a969a9b5e399e58b6871975b76743ca535f1ce64673c707",
     "csrc/fvna_runtime.hip": "205bfd4382d92ca969af3c5710c773d27af5000d46223750f815c9002ca3b582",
     "build.py": "02eda4061ab4ab18fbd0c2e868524ec4e9acf39f5fa26d0513e48c2fca74259e",

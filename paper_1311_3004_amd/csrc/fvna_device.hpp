@@ -413,11 +413,15 @@ __device__ __forceinline__ T mc_half(T th)
 // division by alpha.  Scaling the min/max by alpha (and flipping them when
 // alpha < 0) gives, with g the sign of alpha,
 //   psi alpha = g max(0, min((|alpha| + g u)/4, |alpha|, g u)),
-// which is 0 for alpha = 0.  The signs are bit operations on the high word;
-// /4 is exact (ldexp); 1/n is needed for families 1 and 2 only (n = 1 for
-// family 3), and both come from one reciprocal of n1 n2 >= 1 (hr_split).
-// This saves the three reciprocals of alpha^p n^p -- on this chip an FP64
-// reciprocal estimate occupies the SIMD four times as long as an FMA.
+// which is 0 for alpha = 0.  g u is formed as u * copysign(1, alpha), exact,
+// and a multiply's result, which the compiler knows to be a canonical
+// number (min/max in IEEE mode need canonical operands; a bit flip would
+// cost a quieting instruction at each of them); the result takes alpha's
+// sign by copysign; /4 is exact (ldexp).  1/n is needed for families 1 and 2
+// only (n = 1 for family 3), and both come from one reciprocal of
+// n1 n2 >= 1 (hr_split).  This saves the three reciprocals of alpha^p n^p --
+// on this chip an FP64 reciprocal estimate occupies the SIMD four times as
+// long as an FMA.
 __device__ __forceinline__ double mc_scaled(double a, double u)
 {
     const double gu = u * __builtin_copysign(1.0, a);
