@@ -269,10 +269,11 @@ __device__ __forceinline__ bool step_owed(const Clock* c, int force)
 // the x1 sweep of the row its side rule names (mirrored rows with M2
 // negated), which is the side rule applied to the x1-swept state.
 //
-// TAIL: the last nx mod 60 columns (rem) would fill a 60-column strip only
-// in part (256 columns: 16 of 60).  Their tiles instead pack tailp12 planes
-// into one wavefront: lane segments of w = rem + 4 lanes, segment s holding
-// columns c0 - 2 .. c0 + rem + 1 of plane kg tailp12 + s.  The lane shifts
+// Packed tail: the last nx mod 60 columns (rem) would fill a 60-column strip
+// only in part (256 columns: 16 of 60).  Their tiles instead pack tailp12
+// planes into one wavefront: lane segments of w = rem + 4 lanes, segment s
+// holding columns c0 - 2 .. c0 + rem + 1 of plane kg tailp12 + s (a full
+// strip is the case of one 64-lane segment, sweep12_lanes).  The lane shifts
 // run across segment ends; what crosses them reaches only the two end lanes
 // of a segment, which are its halo, exactly as at the ends of a full strip.
 // Lanes of no segment or past the last plane read a real cell and store and
