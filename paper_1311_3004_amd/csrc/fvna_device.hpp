@@ -82,6 +82,47 @@ struct Clock {
 // once, so the launch costs one round trip: the attempt's largest speed and
 // flags are taken (and cleared for the next attempt) whether or not the
 // attempt counts -- a step launch that had nothing to do left them at zero.
+// The decision itself, as a function: the clock state h an attempt ran with,
+// the bits of its largest wave speed and its flags -> the state after it.
+__device__ __forceinline__ Clock control_next(Clock h, unsigned long long sb, unsigned flags, int fixed_dt,
+                                              double cfl_target, double cfl_max, int max_retries, int nbuf)
+{
+    h.smax_bits = 0;
+    h.flags = 0;
+    if (h.status != 0 || h.accepted >= h.target) return h;
+    const double smax = __longlong_as_double((long long)sb);
+    const long long step = h.accepted;
+    h.attempts += 1;
+    if (flags & FLAG_NONHYP) { h.status = ST_NONHYP; h.status_step = step; return h; }
+    if ((flags & FLAG_NONFINITE) || !(smax <= 1.7976931348623157e308)) {
+        h.status = ST_NONFINITE;
+        h.status_step = step;
+        return h;
+    }
+    const double dt = h.dt;
+    const double nu = dt * smax;
+    h.nu_last = nu;
+    if (!fixed_dt && nu > cfl_max) {
+        h.rejected += 1;
+        h.retries += 1;
+        if (h.retries > max_retries) { h.status = ST_RETRIES; h.status_step = step; return h; }
+        h.dt = dt * cfl_target / nu;
+        return h;
+    }
+    h.retries = 0;
+    h.t = h.t + dt;
+    h.accepted = step + 1;
+    h.cur = h.cur + 1 == nbuf ? 0 : h.cur + 1;
+    const long long n = h.nu_count + 1;
+    h.nu_count = n;
+    const double dev = nu - h.nu_mean;
+    const double mean = h.nu_mean + dev / (double)n;
+    h.nu_mean = mean;
+    h.nu_m2 = h.nu_m2 + dev * (nu - mean);
+    if (!fixed_dt && smax > 0.0) h.dt = dt * cfl_target / nu;
+    return h;
+}
+
 __device__ __forceinline__ void control_attempt(Clock* c, int fixed_dt, double cfl_target, double cfl_max,
                                                 int max_retries, int nbuf)
 {
@@ -89,34 +130,38 @@ __device__ __forceinline__ void control_attempt(Clock* c, int fixed_dt, double c
     const unsigned flags = atomicExch(&c->flags, 0u);
     const Clock h = *c;
     if (h.status != 0 || h.accepted >= h.target) return;
-    const double smax = __longlong_as_double((long long)sb);
-    c->attempts = h.attempts + 1;
-    if (flags & FLAG_NONHYP) { c->status = ST_NONHYP; c->status_step = h.accepted; return; }
-    if ((flags & FLAG_NONFINITE) || !(smax <= 1.7976931348623157e308)) {
-        c->status = ST_NONFINITE;
-        c->status_step = h.accepted;
-        return;
-    }
-    const double nu = h.dt * smax;
-    c->nu_last = nu;
-    if (!fixed_dt && nu > cfl_max) {
-        c->rejected = h.rejected + 1;
-        c->retries = h.retries + 1;
-        if (h.retries + 1 > max_retries) { c->status = ST_RETRIES; c->status_step = h.accepted; return; }
-        c->dt = h.dt * cfl_target / nu;
-        return;
-    }
-    c->retries = 0;
-    c->t = h.t + h.dt;
-    c->accepted = h.accepted + 1;
-    c->cur = h.cur + 1 == nbuf ? 0 : h.cur + 1;
-    const long long n = h.nu_count + 1;
-    c->nu_count = n;
-    const double dev = nu - h.nu_mean;
-    const double mean = h.nu_mean + dev / (double)n;
-    c->nu_mean = mean;
-    c->nu_m2 = h.nu_m2 + dev * (nu - mean);
-    if (!fixed_dt && smax > 0.0) c->dt = h.dt * cfl_target / nu;
+    *c = control_next(h, sb, flags, fixed_dt, cfl_target, cfl_max, max_retries, nbuf);
+}
+
+// Attempts that take the previous attempt's decision in their own prologue
+// (k_step with pos >= 1): beside the clock, in the same allocation, two
+// alternating copies of the clock state and two more CFL slots (slot 0 is the
+// clock's own smax_bits / flags).
+struct CflSlot { unsigned long long smax_bits; unsigned int flags, pad; };
+struct ClockAux { Clock shadow[2]; CflSlot slot[2]; };
+constexpr size_t CLOCK_AUX_OFFSET = 256;           // bytes after the clock
+__device__ __forceinline__ ClockAux* clock_aux(Clock* c)
+{
+    return (ClockAux*)((char*)c + CLOCK_AUX_OFFSET);
+}
+__device__ __forceinline__ void cfl_slot(Clock* c, int k, unsigned long long*& sb, unsigned int*& fl)
+{
+    if (k == 0) { sb = &c->smax_bits; fl = &c->flags; }
+    else { CflSlot& q = clock_aux(c)->slot[k - 1]; sb = &q.smax_bits; fl = &q.flags; }
+}
+
+// What one attempt runs with: the time, step, buffer and domain offset of
+// its clock state, and where its largest wave speed and flags go.
+struct Attempt {
+    double t, dt;
+    long long x_off;
+    int cur;
+    unsigned long long* smax;
+    unsigned int* flags;
+};
+__device__ __forceinline__ Attempt attempt_of(const Clock& h, unsigned long long* sb, unsigned int* fl)
+{
+    return Attempt{h.t, h.dt, h.x_off, h.cur, sb, fl};
 }
 
 // Everything a wavefront needs to know about its simulation.
@@ -721,7 +766,7 @@ struct Pace {
 //         segments take the general path.  Both paths evaluate every cell
 //         with the same arithmetic, so results do not depend on the path.
 template <typename S, typename T, int AXI, bool EDGE, bool LEAN>
-__device__ __forceinline__ void march(const SimDesc& d, int strip, int seg)
+__device__ __forceinline__ void march(const SimDesc& d, int strip, int seg, const Attempt& at)
 {
     using C = Codec<S, T>;
     const int lane = threadIdx.x & (WAVE - 1);
@@ -730,11 +775,10 @@ __device__ __forceinline__ void march(const SimDesc& d, int strip, int seg)
     const int col = c0 - HALO + lane;
     int r0, r1;
     seg_bounds(d, seg, r0, r1);
-    const Clock* clk = d.clk;
-    const double tn = clk->t;
-    const double tx0 = taylor_x0(d, clk->x_off);
-    const T dt = (T)clk->dt;
-    const int cur = clk->cur;
+    const double tn = at.t;
+    const double tx0 = taylor_x0(d, at.x_off);
+    const T dt = (T)at.dt;
+    const int cur = at.cur;
     const long long plane = d.plane;
     const size_t pitch = (size_t)d.pitch;
     const S* __restrict__ inR = (const S*)d.buf[cur];
@@ -1119,16 +1163,16 @@ __device__ __forceinline__ void march(const SimDesc& d, int strip, int seg)
     const bool anyh = __any(hx || hy);
     const bool anyf = __any(fx || fy);
     if (lane == 0) {
-        atomicMax(&d.clk->smax_bits, (unsigned long long)__double_as_longlong(cfl_speed<T>(m)));
+        atomicMax(at.smax, (unsigned long long)__double_as_longlong(cfl_speed<T>(m)));
         const unsigned fl = (anyh ? FLAG_NONHYP : 0u) | (anyf ? FLAG_NONFINITE : 0u);
-        if (fl) atomicOr(&d.clk->flags, fl);
+        if (fl) atomicOr(at.flags, fl);
     }
 }
 
 // Interior strips (no ghost column, no x override) take the EDGE = false
 // variant; segments whose rows are all real rows take the lean path.
 template <typename S, typename T, int AXI>
-__device__ __forceinline__ void march_tile(const SimDesc& d, int strip, int seg)
+__device__ __forceinline__ void march_tile(const SimDesc& d, int strip, int seg, const Attempt& at)
 {
     const int c0 = strip * OUTW;
     const bool interior = d.bc[0] == BC_PERIODIC || (c0 - HALO >= 0 && c0 + OUTW + HALO - 1 <= d.nx - 1);
@@ -1137,11 +1181,11 @@ __device__ __forceinline__ void march_tile(const SimDesc& d, int strip, int seg)
     const bool lean = r0 >= HALO && r1 + HALO <= d.ny &&
                       (long long)(r1 - r0 + 2 * HALO) * d.pitch * (long long)sizeof(S) < (1ll << 31);
     if (interior) {
-        if (lean) march<S, T, AXI, false, true>(d, strip, seg);
-        else march<S, T, AXI, false, false>(d, strip, seg);
+        if (lean) march<S, T, AXI, false, true>(d, strip, seg, at);
+        else march<S, T, AXI, false, false>(d, strip, seg, at);
     } else {
-        if (lean) march<S, T, AXI, true, true>(d, strip, seg);
-        else march<S, T, AXI, true, false>(d, strip, seg);
+        if (lean) march<S, T, AXI, true, true>(d, strip, seg, at);
+        else march<S, T, AXI, true, false>(d, strip, seg, at);
     }
 }
 

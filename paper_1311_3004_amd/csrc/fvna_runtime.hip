@@ -46,6 +46,31 @@ __global__ void k_ctrl(SimDesc d)
     if (threadIdx.x == 0) control(d);
 }
 
+// Closing decision of a captured graph whose attempts 1 .. last took the one
+// before them in their prologue (k_step, pos >= 1): the decision on attempt
+// `last` from its shadow state and CFL slot goes into the clock, and every
+// CFL slot is cleared for the next graph.
+#ifndef FVNA_FOLD_CONTROL
+#define FVNA_FOLD_CONTROL 1
+#endif
+__global__ void k_ctrl_fold(SimDesc d, int last)
+{
+    if (threadIdx.x != 0) return;
+    Clock* c = d.clk;
+    ClockAux* aux = clock_aux(c);
+    const Clock prev = last == 0 ? *c : aux->shadow[last & 1];
+    unsigned long long* sb;
+    unsigned int* fl;
+    cfl_slot(c, last % 3, sb, fl);
+    const unsigned long long s = *sb;
+    const unsigned int f = *fl;
+    *c = control_next(prev, s, f, d.fixed_dt, d.cfl_target, d.cfl_max, d.max_retries, 2);
+    aux->slot[0].smax_bits = 0ull;
+    aux->slot[0].flags = 0u;
+    aux->slot[1].smax_bits = 0ull;
+    aux->slot[1].flags = 0u;
+}
+
 __global__ void k_ctrl_batch(const SimDesc* __restrict__ descs, int n)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -520,9 +545,11 @@ size_t state_bytes_of(const fvna_params* p)
     return align_up((size_t)3 * (size_t)pitch_of(p) * (size_t)p->ny * elem_size(p->precision), ALIGN);
 }
 
-// scratch layout: [Clock][sum partials][sum out][source table][staging]
+// scratch layout: [Clock, ClockAux][sum partials][sum out][source table][staging]
 constexpr size_t OFF_CLOCK = 0;
-constexpr size_t OFF_PART = 256;
+constexpr size_t OFF_PART = 768;
+static_assert(CLOCK_AUX_OFFSET >= sizeof(Clock) && CLOCK_AUX_OFFSET + sizeof(ClockAux) <= OFF_PART,
+              "clock and its shadow states must fit before the partial sums");
 constexpr size_t OFF_SUMOUT = OFF_PART + align_up(SUM_BLOCKS * 3 * sizeof(double), ALIGN);
 constexpr size_t OFF_SRCTAB = OFF_SUMOUT + 256;
 
@@ -614,7 +641,7 @@ std::map<std::tuple<int, int, int, int>, int> g_tune;
 }  // namespace
 
 struct Launcher {
-    void (*step)(const SimDesc&, int force, hipStream_t);
+    void (*step)(const SimDesc&, int force, int pos, hipStream_t);
     void (*step_batch)(const SimDesc*, const TileRef*, int ntiles, int force, hipStream_t);
     void (*dry)(const SimDesc&, hipStream_t);
     void (*imp)(const SimDesc&, const double*, int, int, int, double, int, hipStream_t);
@@ -629,10 +656,10 @@ template <typename S, typename T, int AXI>
 Launcher make_launcher()
 {
     Launcher L;
-    L.step = [](const SimDesc& d, int force, hipStream_t s) {
+    L.step = [](const SimDesc& d, int force, int pos, hipStream_t s) {
         const int tiles = d.strips * d.segs;
         const int blocks = (tiles + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
-        hipLaunchKernelGGL((k_step<S, T, AXI>), dim3(blocks), dim3(256), 0, s, d, force);
+        hipLaunchKernelGGL((k_step<S, T, AXI>), dim3(blocks), dim3(256), 0, s, d, force, pos);
     };
     L.step_batch = [](const SimDesc* descs, const TileRef* tiles, int ntiles, int force, hipStream_t s) {
         const int blocks = (ntiles + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
@@ -733,7 +760,7 @@ struct fvna_ctx {
 // in the same launch, if any).
 static void launch_attempt(fvna_ctx* c, hipStream_t s)
 {
-    c->L.step(c->d, 0, s);
+    c->L.step(c->d, 0, 0, s);
     if (c->recording) c->L.ctrl_record(c->d, c->rec, s);
     else hipLaunchKernelGGL(k_ctrl, dim3(1), dim3(64), 0, s, c->d);
 }
@@ -754,7 +781,14 @@ static fvna_status build_graph(fvna_ctx* c)
 {
     if (c->exec) return FVNA_OK;
     HIP_TRY(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
-    for (int k = 0; k < GRAPH_CHUNK; ++k) launch_attempt(c, c->cap);
+    if (c->recording || !FVNA_FOLD_CONTROL) {
+        for (int k = 0; k < GRAPH_CHUNK; ++k) launch_attempt(c, c->cap);
+    } else {
+        // attempts 1 .. GRAPH_CHUNK-1 take the decision on the attempt before
+        // them in their prologue; one controller launch closes the graph
+        for (int k = 0; k < GRAPH_CHUNK; ++k) c->L.step(c->d, 0, k, c->cap);
+        hipLaunchKernelGGL(k_ctrl_fold, dim3(1), dim3(64), 0, c->cap, c->d, GRAPH_CHUNK - 1);
+    }
     hipGraph_t g = nullptr;
     HIP_TRY(hipStreamEndCapture(c->cap, &g));
     c->graph = g;
@@ -1316,7 +1350,7 @@ fvna_status fvna_time_step_kernel(fvna_ctx* c, int32_t reps, double* ms_per_laun
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     HIP_TRY(hipEventRecord(e0, c->stream));
-    for (int k = 0; k < reps; ++k) c->L.step(c->d, 1, c->stream);
+    for (int k = 0; k < reps; ++k) c->L.step(c->d, 1, 0, c->stream);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(e1, c->stream));
     HIP_TRY(hipEventSynchronize(e1));
