@@ -44,19 +44,19 @@ BYTES_PER_CELL = {"f64": 48, "f32": 24, "f32_f16store": 12, "f32_bf16store": 12}
 # after any change they report null until profiled again.
 PMC_SOURCES = ("csrc/fvna_device.hpp", "csrc/fvna_step.hpp", "csrc/fvna_runtime.hip", "build.py")
 _PROFILED = {
-    "csrc/fvna_device.hpp": "c729c2c4f4e3c897eadd7999c90205e4af7dba1c2c9c84628fc1c021f17fa238",
-    "csrc/fvna_step.hpp": "bdaa87da40e74c672a969a9b5e399e58b6871975b76743ca535f1ce64673c707",
-    "csrc/fvna_runtime.hip": "205bfd4382d92ca969af3c5710c773d27af5000d46223750f815c9002ca3b582",
+    "csrc/fvna_device.hpp": "e0bcf378bde9a618aaf1436cbaacaa156849429748305b2f7d60c1c5da6f18f7",
+    "csrc/fvna_step.hpp": "a9e84437ccfeefe0500bc34f950718571f6c39e84c9e7b8d6134cc1fc4995563",
+    "csrc/fvna_runtime.hip": "3918adf77604081eac641ee11673ca1e7aff655fd1be5d44cebae7fa6e217a1c",
     "build.py": "02eda4061ab4ab18fbd0c2e868524ec4e9acf39f5fa26d0513e48c2fca74259e",
 }
 PMC = {
     # profiles/k_step_f64_gaussian4096.md
-    "k_step<double,double,0>": {"nx": 4096, "ny": 4096, "fetch_bytes": 4.2195e+08, "write_bytes": 4.0521e+08,
-                                "valu_lane_ops_per_cell": 400.0, "valu_issue_cycles_per_cell": 26.51,
+    "k_step<double,double,0>": {"nx": 4096, "ny": 4096, "fetch_bytes": 4.2244e+08, "write_bytes": 4.0527e+08,
+                                "valu_lane_ops_per_cell": 399.6, "valu_issue_cycles_per_cell": 26.49,
                                 "sources": _PROFILED},
     # profiles/k_step_f32_gaussian4096.md
-    "k_step<float,float,0>": {"nx": 4096, "ny": 4096, "fetch_bytes": 2.1633e+08, "write_bytes": 2.0419e+08,
-                              "valu_lane_ops_per_cell": 302.9, "valu_issue_cycles_per_cell": 20.03,
+    "k_step<float,float,0>": {"nx": 4096, "ny": 4096, "fetch_bytes": 2.1641e+08, "write_bytes": 2.0448e+08,
+                              "valu_lane_ops_per_cell": 303.1, "valu_issue_cycles_per_cell": 20.05,
                               "sources": _PROFILED},
 }
 
