@@ -210,6 +210,71 @@ def test_rejection_path_matches_oracle(orc):
     assert max_rel(g, o) <= 1e-10
 
 
+def _graph_and_single_attempts(w, steps, precision="f64", **over):
+    """The same run enqueued as one fvna_step(steps) call -- a captured graph
+    of 32 attempts, whose attempts after the first take the decision on the
+    attempt before them in their own prologue, then single attempts -- and as
+    `steps` calls of fvna_step(1), every attempt followed by its own controller
+    launch.  Returns both (state, stats) pairs."""
+    from paper_1311_3004_amd import fvna
+    out = []
+    for calls in (1, steps):
+        s = fvna.sim_from_workload(w, precision=precision, **over)
+        for _ in range(calls):
+            s.fvna_step(steps // calls)
+        s.fvna_sync(allow_device_errors=True)
+        out.append((s.fvna_get_state(allow_device_errors=True), s.fvna_get_stats(allow_device_errors=True)))
+        s.fvna_destroy()
+    return out
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_decisions_in_graph_prologues_equal_single_attempts(orc, precision):
+    """A first step three times too large, 40 steps: the rejection and every
+    later decision taken inside a captured graph give bitwise the state and
+    statistics of single attempts, and the oracle's run (FP64 to 1e-10)."""
+    w = pulse_workload(90, 60, ("extrap0",) * 4, seed=13)
+    dt_si = 3.0 * w["dx"] / w["medium"]["c0"]
+    _say(f"case: decisions in graph prologues vs single attempts, {precision}, 40 steps")
+    (ga, sa), (gb, sb) = _graph_and_single_attempts(w, 40, precision, dt0=dt_si)
+    assert sa["status"] == 0 and sa["steps"] == 40 and sa["rejected"] == 1
+    for k in ("t", "dt_next", "nu_last", "nu_mean", "nu_std", "steps", "rejected", "status"):
+        assert sa[k] == sb[k], k
+    for a, b in zip(ga, gb):
+        assert np.array_equal(a, b)
+    if precision == "f64":
+        o, info = run_oracle(orc, w, 40, dt_si=dt_si)
+        med = w["medium"]
+        g = (ga[0] / med["rho0"], ga[1] / (med["rho0"] * med["c0"]), ga[2] / (med["rho0"] * med["c0"]))
+        assert info["rejected"] == 1 and max_rel(g, o) <= 1e-10
+
+
+def test_failures_decided_in_graph_prologues():
+    """A non-hyperbolic state, and a rejection with no retries allowed, met by
+    the first attempt of a 40-step call: the status, the step it names and the
+    kept state are those of single attempts."""
+    from paper_1311_3004_amd import fvna
+    w = pulse_workload(64, 64, ("extrap0",) * 4, seed=17)
+    rp = w["state"][0].copy()
+    rp[30:34, 30:34] = -0.6 * w["medium"]["rho0"]
+    wn = dict(w, state=(rp, w["state"][1], w["state"][2]))
+    _say("case: non-hyperbolic state, 40 steps in one call and in single calls")
+    (ga, sa), (gb, sb) = _graph_and_single_attempts(wn, 40, dt0=1e-8)
+    assert sa["status"] == sb["status"] == fvna.E_NONHYPERBOLIC
+    assert sa["steps"] == sb["steps"] == 0 and sa["status_step"] == sb["status_step"] == 0
+    assert np.array_equal(ga[0], rp)
+    for a, b in zip(ga, gb):
+        assert np.array_equal(a, b)
+    _say("case: rejection with max_retries = 0, 40 steps in one call and in single calls")
+    dt_si = 3.0 * w["dx"] / w["medium"]["c0"]
+    (ga, sa), (gb, sb) = _graph_and_single_attempts(w, 40, dt0=dt_si, max_retries=0)
+    assert sa["status"] == sb["status"] == fvna.E_RETRIES
+    assert sa["steps"] == sb["steps"] == 0 and sa["rejected"] == sb["rejected"] == 1
+    assert np.array_equal(ga[0], w["state"][0])            # the state kept
+    for a, b in zip(ga, gb):
+        assert np.array_equal(a, b)
+
+
 def test_nonhyperbolic_state_is_reported(orc):
     from paper_1311_3004_amd import fvna
     w = pulse_workload(64, 64, ("extrap0",) * 4, seed=17)
