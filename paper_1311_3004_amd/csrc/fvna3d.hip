@@ -15,10 +15,16 @@
 //               carried in registers, x1 neighbours over DPP, x2 neighbours
 //               loaded;
 //   k3_ctrl     accept or reject (control_attempt), one thread.
-// Three state buffers X0, X1, X2 and the device clock's cur = c: the sweeps
-// go X[c] -> X[c+1] -> X[c+2], the source X[c+2] -> X[c+1], and an accepted
-// step makes X[c+1] current (indices modulo 3).  Steps are replayed from a
-// captured HIP graph; the host waits once per fvna3_step call.
+// Three state buffers X0, X1, X2 and the device clock's cur = c.  The source
+// leaves the density as the x3 sweep made it, so a state keeps its density
+// and its momenta in different buffers: density in X[1-c], momenta in X[-c]
+// (indices modulo 3).  The x1-x2 sweep writes all four fields to the third
+// buffer X[2-c]; the x3 sweep writes its density into X[-c] and its momenta
+// into X[1-c] (planes the current state does not use); the source writes the
+// momenta into X[2-c] and no density.  An accepted step advances c by one,
+// which makes exactly these the new state's buffers; a rejected one leaves
+// the current state untouched.  Steps are replayed from a captured HIP graph;
+// the host waits once per fvna3_step call.
 // Ghost values follow the side rule of their axis applied to the state of
 // the stage that needs them (Q^n for x1, the x1-swept state for x2, the
 // x2-swept state for x3, the x3-swept state for the source).
@@ -39,6 +45,11 @@ namespace {
 
 constexpr int HALO12 = 2;                      // x1 stencil: two interfaces each side
 constexpr int OUT12 = WAVE - 2 * HALO12;       // 60 output columns per x1-x2 wavefront
+
+// Buffer roles for clock cur = c (see the file's header).
+__device__ __forceinline__ int buf_rho(int c) { return c == 0 ? 1 : c == 1 ? 0 : 2; }
+__device__ __forceinline__ int buf_mom(int c) { return c == 0 ? 0 : c == 1 ? 2 : 1; }
+__device__ __forceinline__ int buf_x12(int c) { return c == 0 ? 2 : c == 1 ? 1 : 0; }
 
 struct Desc3 {
     int n[3];                  // nx, ny, nz
@@ -319,8 +330,9 @@ __device__ __forceinline__ void sweep12_tile(const Desc3& d, int tile, const Clo
     const int r0 = seg * d.rows12, r1 = min(r0 + d.rows12, ny);
     const T dt = (T)clk->dt;
     const int cur = clk->cur;
-    const T* in = (const T*)d.buf[cur];
-    T* out = (T*)d.buf[cur == 2 ? 0 : cur + 1];
+    const T* inR = (const T*)d.buf[buf_rho(cur)];
+    const T* inM = (const T*)d.buf[buf_mom(cur)];
+    T* out = (T*)d.buf[buf_x12(cur)];
     const T beta = (T)d.beta;
     const bool perx = d.bc[0] == FVNA_BC_PERIODIC, pery = d.bc[2] == FVNA_BC_PERIODIC;
     bool xneg;
@@ -335,13 +347,15 @@ __device__ __forceinline__ void sweep12_tile(const Desc3& d, int tile, const Clo
     // raw Q^n of the row that row v stands for (side rule along x2)
     // this lane's plane and column, fixed over the march (the row offset
     // added per row is the same for every lane)
-    const T* __restrict__ in_l = in + (zoff + (size_t)scol);
+    const T* __restrict__ inR_l = inR + (zoff + (size_t)scol);
+    const T* __restrict__ inM_l = inM + (zoff + (size_t)scol);
     T* __restrict__ out_l = out + (zoff + (size_t)(out_lane ? col : 0));
     auto load_row = [&](int v) -> Q4<T> {
         bool yneg;
         const int sr = side_map(d, 1, v, yneg);
-        const T* q = in_l + (size_t)sr * (size_t)d.pitch;
-        return Q4<T>{q[0], q[pl], q[2 * pl], q[3 * pl]};
+        const size_t ro = (size_t)sr * (size_t)d.pitch;
+        const T* m = inM_l + ro;
+        return Q4<T>{inR_l[ro], m[pl], m[2 * pl], m[3 * pl]};
     };
     auto xsweep = [&](Q4<T> q) -> Q4<T> {
         q.n = xs * q.n;
@@ -471,8 +485,9 @@ __global__ __launch_bounds__(256) void k3_sweep3(Desc3 d, int force)
     const int k0 = seg * d.planes3, k1 = min(k0 + d.planes3, nz);
     const T dt = (T)clk->dt;
     const int cur = clk->cur;
-    const T* in = (const T*)d.buf[cur == 2 ? 0 : cur + 1];
-    T* out = (T*)d.buf[cur == 0 ? 2 : cur - 1];
+    const T* in = (const T*)d.buf[buf_x12(cur)];
+    T* outR = (T*)d.buf[buf_mom(cur)];          // density plane of the momentum buffer
+    T* outM = (T*)d.buf[buf_rho(cur)];          // momentum planes of the density buffer
     const T beta = (T)d.beta;
     const bool perz = d.bc[4] == FVNA_BC_PERIODIC;
     const size_t pl = (size_t)d.plane;
@@ -499,10 +514,10 @@ __global__ __launch_bounds__(256) void k3_sweep3(Desc3 d, int force)
         const int kk = v - 2;
         if (kk >= k0 && col < nx) {
             const size_t w = (size_t)kk * zstride + (size_t)j * (size_t)d.pitch + (size_t)col;
-            out[w] = dn.R;
-            out[pl + w] = dn.a;
-            out[2 * pl + w] = dn.b;
-            out[3 * pl + w] = dn.n;
+            outR[w] = dn.R;
+            outM[pl + w] = dn.a;
+            outM[2 * pl + w] = dn.b;
+            outM[3 * pl + w] = dn.n;
         }
     };
     Q4<T> p0 = load_plane(v0), p1 = load_plane(v0 + 1);
@@ -522,7 +537,8 @@ __global__ __launch_bounds__(256) void k3_sweep3(Desc3 d, int force)
 
 // ---------------------------------------------------------------------------
 // Source (3-D form of eq. fs:source, forward Euler): M_c += dt delta~ lap(u_c),
-// 7-point Laplacian of u_c = M_c / (1 + R), R unchanged.  A block of
+// 7-point Laplacian of u_c = M_c / (1 + R); the density is not rewritten (it
+// stays where the x3 sweep put it).  A block of
 // SRC_ROWS (= s) wavefronts takes rows s g .. s g + s - 1 of one 64-column
 // strip over planes k0 .. k1 - 1: lane = column, wave = row.  Per plane each
 // wave publishes its row's velocities in LDS (the first and last waves also
@@ -571,8 +587,9 @@ __global__ __launch_bounds__(WAVE * SRC_ROWS) void k3_source(Desc3 d, int force)
     const int k0 = seg * d.planes4, k1 = min(k0 + d.planes4, nz);
     const T dt = (T)clk->dt;
     const int cur = clk->cur;
-    const T* in = (const T*)d.buf[cur == 0 ? 2 : cur - 1];
-    T* out = (T*)d.buf[cur == 2 ? 0 : cur + 1];
+    const T* inR = (const T*)d.buf[buf_mom(cur)];     // the x3 sweep's density ...
+    const T* inM = (const T*)d.buf[buf_rho(cur)];     // ... and momenta
+    T* out = (T*)d.buf[buf_x12(cur)];                 // momenta only
     const T kd = dt * (T)d.delta;
     const size_t pl = (size_t)d.plane;
     const size_t zstride = (size_t)ny * (size_t)d.pitch;
@@ -588,7 +605,7 @@ __global__ __launch_bounds__(WAVE * SRC_ROWS) void k3_source(Desc3 d, int force)
     const int hslot = wave == 0 ? 0 : SRC_ROWS + 1;
     // raw cell at element offset o with the mirrored components negated
     auto raw = [&](size_t o, bool neg1, bool neg2, bool neg3) -> Q4<T> {
-        Q4<T> q{in[o], in[pl + o], in[2 * pl + o], in[3 * pl + o]};
+        Q4<T> q{inR[o], inM[pl + o], inM[2 * pl + o], inM[3 * pl + o]};
         if (neg1) q.n = -q.n;
         if (neg2) q.a = -q.a;
         if (neg3) q.b = -q.b;
@@ -655,7 +672,6 @@ __global__ __launch_bounds__(WAVE * SRC_ROWS) void k3_source(Desc3 d, int force)
         const T l3 = lap(uc.u3, xl.u3, xh.u3, yl.u3, yh.u3, ub.u3, ua.u3);
         if (col < nx && j < ny) {
             const size_t o = (size_t)k * zstride + (size_t)j * (size_t)d.pitch + (size_t)col;
-            out[o] = q0.R;
             out[pl + o] = fma_(kd, l1, q0.n);
             out[2 * pl + o] = fma_(kd, l2, q0.a);
             out[3 * pl + o] = fma_(kd, l3, q0.b);
@@ -719,7 +735,9 @@ __global__ void k3_import(Desc3 d, const double* __restrict__ src, int field, do
     if (i >= d.pitch) return;
     const int rows = d.n[1] * d.n[2];
     for (int r = blockIdx.y; r < rows; r += gridDim.y) {
-        T* dst = (T*)d.buf[0] + (size_t)field * (size_t)d.plane + (size_t)r * (size_t)d.pitch;
+        // the state of clock cur = 0 (set after the import)
+        T* dst = (T*)d.buf[field == 0 ? buf_rho(0) : buf_mom(0)] + (size_t)field * (size_t)d.plane +
+                 (size_t)r * (size_t)d.pitch;
         dst[i] = i < d.n[0] ? (T)(src[(size_t)r * d.n[0] + i] / denom) : T(0);
     }
 }
@@ -730,7 +748,8 @@ __global__ void k3_export(Desc3 d, double* __restrict__ dst, int field, double f
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= d.n[0]) return;
     const int rows = d.n[1] * d.n[2];
-    const T* base = (const T*)d.buf[d.clk->cur] + (size_t)field * (size_t)d.plane;
+    const int cur = d.clk->cur;
+    const T* base = (const T*)d.buf[field == 0 ? buf_rho(cur) : buf_mom(cur)] + (size_t)field * (size_t)d.plane;
     for (int r = blockIdx.y; r < rows; r += gridDim.y)
         dst[(size_t)r * d.n[0] + i] = (double)base[(size_t)r * (size_t)d.pitch + i] * factor;
 }
