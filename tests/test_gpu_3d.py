@@ -30,13 +30,17 @@ def _state(nx, ny, nz, seed):
     return R, M
 
 
-def _run_pair(precision, steps, fixed, dt_cells=0.6, shape=(20, 14, 10), seed=3, bc=BC):
+def _run_pair(precision, steps, fixed, dt_cells=0.6, shape=(20, 14, 10), seed=3, bc=BC, first_dt_cells=None):
+    """first_dt_cells (adaptive runs): the first attempt's dt in cells / c0
+    instead of the dry pass's."""
     from paper_1311_3004_amd import fvna3d as f3
     from oracle import oracle3d as o3
     nx, ny, nz = shape
     R, M = _state(nx, ny, nz, seed)
     rho0, c0 = MED["rho0"], MED["c0"]
-    dt_si = dt_cells * DX / c0 if fixed else 0.0
+    if not fixed and first_dt_cells is not None:
+        dt_cells = first_dt_cells
+    dt_si = dt_cells * DX / c0 if (fixed or first_dt_cells is not None) else 0.0
     p = f3.make_params(nx, ny, nz, DX, MED, bc=bc, precision=precision, fixed_dt=fixed, dt0=dt_si)
     s = f3.Sim3(p)
     s.fvna3_set_state(R * rho0, *[m * rho0 * c0 for m in M])
@@ -46,7 +50,7 @@ def _run_pair(precision, steps, fixed, dt_cells=0.6, shape=(20, 14, 10), seed=3,
     s.fvna3_destroy()
     g = (g[0] / rho0,) + tuple(m / (rho0 * c0) for m in g[1:])
     po = o3.make_params(nx, ny, nz, MED["beta"], MED["delta"] / (c0 * DX), bc=bc, fixed_dt=fixed)
-    o, info = o3.run(po, [R] + M, steps, dt=dt_cells if fixed else 0.0)
+    o, info = o3.run(po, [R] + M, steps, dt=dt_cells if (fixed or first_dt_cells is not None) else 0.0)
     assert info["status"] == 0 and st["steps"] == steps
     err = max(np.max(np.abs(a - b)) for a, b in zip(g, o)) / np.max(np.abs(o[0]))
     return err, st, info
@@ -93,6 +97,18 @@ def test_3d_packed_tail_vs_oracle(shape, precision, fixed, tol):
     assert err <= tol
     if not fixed:
         assert abs(st["t"] * MED["c0"] / DX - info["t"]) <= 1e-7 * info["t"]
+
+
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-10), ("f32", 2e-6)])
+def test_3d_rejected_first_step_is_redone_from_the_same_state(precision, tol):
+    """A first dt three times the CFL limit: the attempt is rejected, redone
+    from the untouched state with dt nu_W / nu, and the run goes on as in the
+    oracle (the state's density and momenta live in different buffers, and a
+    rejected attempt writes neither of them)."""
+    _say(f"case: 3-D rejected first step, {precision}")
+    err, st, info = _run_pair(precision, 12, False, first_dt_cells=3.0)
+    assert info["rejected"] == 1 and st["rejected"] == 1
+    assert err <= tol, err
 
 
 def test_3d_refuses_bad_parameters():
