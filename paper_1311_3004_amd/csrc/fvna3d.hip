@@ -171,8 +171,8 @@ __device__ __forceinline__ void hr_split4(const W4<T>& w, const T lo[4], const T
     } else {
         pa1 = mc_half(t1 * rcp(w.a1 * q1)) * w.a1;
         pa2 = mc_half(t2 * rcp(w.a2 * q2)) * w.a2;
-        pa3 = mc_half(t3 * rcp(w.a3)) * w.a3;
-        pa4 = mc_half(t4 * rcp(w.a4)) * w.a4;
+        pa3 = mc_unit(w.a3, t3);
+        pa4 = mc_unit(w.a4, t4);
     }
     const T as1 = abs_(w.s1), as2 = abs_(w.s2), as3 = abs_(w.s3);
     const T f1 = fma_(-dt, as1, T(1)) * as1, f2 = fma_(-dt, as2, T(1)) * as2, f3 = fma_(-dt, as3, T(1)) * as3;

@@ -444,10 +444,12 @@ template <> struct Cfl<double> {
 // ratio: theta = t / (alpha n), t = alpha_up X.  The neighbour supplies t, so
 // each lane ships t instead of the full product W_up . W.
 //
-// FP32: psi from theta = t / (alpha n), times alpha.  When alpha = 0 the
-// quotient is x/0 or 0/0, psi is then 0 or 1 (min/max return the non-NaN
-// operand), and the product with alpha is 0 -- the value the guard
-// theta := 0 gives.  So no guard is evaluated.
+// FP32, families 1 and 2: psi from theta = t / (alpha n), times alpha (one
+// reciprocal estimate, a two-quad-cycle instruction in FP32; the shear family
+// takes mc_unit below).  When alpha = 0 the quotient is x/0 or 0/0, psi is
+// then 0 or 1 (min/max return the non-NaN operand), and the product with
+// alpha is 0 -- the value the guard theta := 0 gives.  So no guard is
+// evaluated.
 template <typename T>
 __device__ __forceinline__ T mc_half(T th)
 {
@@ -473,6 +475,24 @@ __device__ __forceinline__ double mc_scaled(double a, double u)
     const double aa = __builtin_fabs(a);
     const double m = max_(0.0, min_(min_(__builtin_ldexp(aa + gu, -2), aa), gu));
     return __builtin_copysign(m, a);
+}
+
+// FP32, a family whose eigenvector is a unit vector (n = 1, X = 1: the shear
+// wave), so t = alpha_up and theta = t / alpha.  With q = (alpha + t)/4, the
+// product psi alpha is max(0, min(q, alpha, t)) for alpha >= 0 and
+// min(0, max(q, alpha, t)) for alpha < 0; both equal
+// med3(0, min(q, alpha, t), max(q, alpha, t)) (when alpha and t differ in sign
+// the minimum is negative and the maximum positive), and it is 0 for
+// alpha = 0.  Five instructions (v_minimum3, v_maximum3 and v_med3 among them)
+// and no reciprocal.  The NaN-propagating minimum and maximum take the
+// neighbour's t as it comes off the lane shift (an IEEE min/max would need it
+// quieted first); t and alpha are finite whenever the state is.
+__device__ __forceinline__ float mc_unit(float a, float t)
+{
+    const float q = (a + t) * 0.25f;
+    const float lo = __builtin_elementwise_minimum(__builtin_elementwise_minimum(q, a), t);
+    const float hi = __builtin_elementwise_maximum(__builtin_elementwise_maximum(q, a), t);
+    return __builtin_amdgcn_fmed3f(0.0f, lo, hi);
 }
 
 // The upwind values t of two neighbouring interfaces a (below) and b (above)
@@ -514,7 +534,7 @@ __device__ __forceinline__ void hr_split(const Wave<T>& w, const T dlo[3], const
     } else {
         pa1 = mc_half(t1 * rcp(w.a1 * n1)) * w.a1;
         pa2 = mc_half(t2 * rcp(w.a2 * n2)) * w.a2;
-        pa3 = mc_half(t3 * rcp(w.a3)) * w.a3;
+        pa3 = mc_unit(w.a3, t3);
     }
     const T as1 = abs_(w.s1), as2 = abs_(w.s2), as3 = abs_(w.s3);
     // correction strengths c_p = 1/2 |s| (1 - dt |s|) phi alpha = |s| (1 - dt |s|) psi alpha
