@@ -33,7 +33,7 @@ BYTES_PER_CELL = {"f64": 48, "f32": 24, "f32_f16store": 12, "f32_bf16store": 12}
 # Counter figures of the step kernels on this workload (4096 x 4096), from
 # rocprofv3 --pmc runs of this script: HBM bytes per launch from FETCH_SIZE,
 # then WRITE_SIZE, each scaled by what the same counter reads for a plain
-# 1 GiB device copy (fetch x2.000, write x1.000), and VALU lane-ops per
+# device copy (fetch x1.988, write x1.000), and VALU lane-ops per
 # cell-update from SQ_INSTS_VALU x 64 / cells, and SIMD issue cycles per
 # cell-update from SQ_ACTIVE_INST_VALU (quad-cycles, summed over waves) x 4 /
 # cells, which also counts the extra cycles of transcendental instructions
@@ -44,19 +44,19 @@ BYTES_PER_CELL = {"f64": 48, "f32": 24, "f32_f16store": 12, "f32_bf16store": 12}
 # after any change they report null until profiled again.
 PMC_SOURCES = ("csrc/fvna_device.hpp", "csrc/fvna_step.hpp", "csrc/fvna_runtime.hip", "build.py")
 _PROFILED = {
-    "csrc/fvna_device.hpp": "e0bcf378bde9a618aaf1436cbaacaa156849429748305b2f7d60c1c5da6f18f7",
+    "csrc/fvna_device.hpp": "854f213066db88703d843e94fc11a394f1ecd65ac8e597ea6dbbc2eeedef452f",
     "csrc/fvna_step.hpp": "a9e84437ccfeefe0500bc34f950718571f6c39e84c9e7b8d6134cc1fc4995563",
     "csrc/fvna_runtime.hip": "3918adf77604081eac641ee11673ca1e7aff655fd1be5d44cebae7fa6e217a1c",
     "build.py": "02eda4061ab4ab18fbd0c2e868524ec4e9acf39f5fa26d0513e48c2fca74259e",
 }
 PMC = {
     # profiles/k_step_f64_gaussian4096.md
-    "k_step<double,double,0>": {"nx": 4096, "ny": 4096, "fetch_bytes": 4.2244e+08, "write_bytes": 4.0527e+08,
+    "k_step<double,double,0>": {"nx": 4096, "ny": 4096, "fetch_bytes": 4.1996e+08, "write_bytes": 4.0523e+08,
                                 "valu_lane_ops_per_cell": 399.6, "valu_issue_cycles_per_cell": 26.49,
                                 "sources": _PROFILED},
     # profiles/k_step_f32_gaussian4096.md
-    "k_step<float,float,0>": {"nx": 4096, "ny": 4096, "fetch_bytes": 2.1641e+08, "write_bytes": 2.0448e+08,
-                              "valu_lane_ops_per_cell": 303.1, "valu_issue_cycles_per_cell": 20.05,
+    "k_step<float,float,0>": {"nx": 4096, "ny": 4096, "fetch_bytes": 2.1502e+08, "write_bytes": 2.0448e+08,
+                              "valu_lane_ops_per_cell": 300.8, "valu_issue_cycles_per_cell": 19.75,
                               "sources": _PROFILED},
 }
 
