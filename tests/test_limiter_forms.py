@@ -10,7 +10,7 @@ form alpha * psi(theta), psi = phi / 2, phi(theta) = max(0, min((1 + theta)/2,
 
 Both are exact algebra (they differ from the textbook form by rounding
 only), and both give 0 for alpha = 0, where the textbook form needs the
-guard theta := 0.  A planted mistake (a dropped /4, a swapped min/max, a
+guard theta := 0.  A planted mistake (a dropped /4, a sign left off u, a
 missing clamp) fails these checks."""
 import numpy as np
 
