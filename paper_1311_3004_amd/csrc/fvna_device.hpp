@@ -182,7 +182,23 @@ struct SimDesc {
     int sr_env;                  // 0: sin^2 ramp in t; 1: packet exp(-(f tau / sr_W)^10)
     double sr_W;                 // packet half-width in periods
     double sr_t2;                // start of the second stage (+inf: none)
+    const void* rinv;            // axisymmetric: 1/(j + 1/2) for rows j = -RINV_PAD .. ny + RINV_PAD - 1,
+                                 // in the arithmetic type (rinv_at)
 };
+
+// 1/r at the centre of row j (r = j + 1/2 cells) from the per-row table the
+// library fills when an axisymmetric grid is created (the correctly rounded
+// quotient).  Read through the constant address space: a scalar load of a
+// row-uniform value, where computing it took a conversion, an add and a
+// reciprocal on the vector unit for each of the three uses per row.  Rows
+// down to -RINV_PAD and up to ny + RINV_PAD - 1 are covered (the warm-up rows
+// of the first and last segment push ghost rows, whose values are not used).
+constexpr int RINV_PAD = 8;
+template <typename T> __device__ __forceinline__ T rinv_at(const SimDesc& d, int j)
+{
+    typedef const __attribute__((address_space(4))) T* ConstT;
+    return ((ConstT)d.rinv)[j + RINV_PAD];
+}
 
 // ---------------------------------------------------------------------------
 // Storage codecs.
@@ -925,7 +941,7 @@ __device__ __forceinline__ void march(const SimDesc& d, int strip, int seg, cons
         o2.R = fma_(-dt, g0 + Gp[0], q.R);
         o2.M = fma_(-dt, g1 + Gp[1], q.M);
         o2.N = fma_(-dt, g2 + Gp[2], q.N);
-        if constexpr (AXI && !GHOST) geometric_half_step(o2, hdt * rcp(T(vr) + T(0.5)));
+        if constexpr (AXI && !GHOST) geometric_half_step(o2, hdt * rinv_at<T>(d, vr));
         return o2;
     };
     auto xsweep = [&](int vr, S ra, S rb, S rc) -> Cell<T> {
@@ -979,7 +995,7 @@ __device__ __forceinline__ void march(const SimDesc& d, int strip, int seg, cons
         out.part.R = fma_(-dt, Gp[0], in.q.R);
         out.part.N = fma_(-dt, Gp[1], in.q.N);
         out.part.M = fma_(-dt, Gp[2], in.q.M);
-        if constexpr (AXI) geometric_half_step(qn, hdt * rcp(T(v - 2) + T(0.5)));
+        if constexpr (AXI) geometric_half_step(qn, hdt * rinv_at<T>(d, v - 2));
         const T irn = rcp(T(1) + qn.R);
         const T un = qn.M * irn, vn = qn.N * irn;
         // source of row j = v-3 (x2-swept rows j-1, j, j+1), then store
@@ -1030,7 +1046,7 @@ __device__ __forceinline__ void march(const SimDesc& d, int strip, int seg, cons
             T oMv, oNv;
             if constexpr (AXI) {
                 // cylindrical vector Laplacian: + (1/r) d/dr of each velocity, - v/r^2
-                const T ir = rcp(T(j) + T(0.5));
+                const T ir = rinv_at<T>(d, j);
                 const T dur = T(0.5) * (uab - ubl), dvr = T(0.5) * (vab - vbl);
                 const T k = dt * delta;
                 oMv = fma_(k, fma_(dur, ir, lapu), in.qs.M);

@@ -218,6 +218,17 @@ __global__ void k_src_table(double* __restrict__ tab, int ny, double f, double F
     tab[4 * (size_t)j + 3] = delay;
 }
 
+// Per-row 1/r of an axisymmetric grid, r = j + 1/2 for rows j = -RINV_PAD ..
+// ny + RINV_PAD - 1 (entry j + RINV_PAD): the correctly rounded FP64
+// quotient, in the arithmetic type of the step.
+template <typename T>
+__global__ void k_rinv_table(T* __restrict__ tab, int ny)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= ny + 2 * RINV_PAD) return;
+    tab[k] = (T)(1.0 / ((double)(k - RINV_PAD) + 0.5));
+}
+
 // Whole clock of one simulation written from its arguments (every field the
 // controller and the step kernel read starts defined, counters at zero).
 __global__ void k_clock_init(Clock* __restrict__ c, double t, double dt, int cur, long long target)
@@ -545,7 +556,7 @@ size_t state_bytes_of(const fvna_params* p)
     return align_up((size_t)3 * (size_t)pitch_of(p) * (size_t)p->ny * elem_size(p->precision), ALIGN);
 }
 
-// scratch layout: [Clock, ClockAux][sum partials][sum out][source table][staging]
+// scratch layout: [Clock, ClockAux][sum partials][sum out][source table][1/r table][staging]
 constexpr size_t OFF_CLOCK = 0;
 constexpr size_t OFF_PART = 768;
 static_assert(CLOCK_AUX_OFFSET >= sizeof(Clock) && CLOCK_AUX_OFFSET + sizeof(ClockAux) <= OFF_PART,
@@ -553,9 +564,30 @@ static_assert(CLOCK_AUX_OFFSET >= sizeof(Clock) && CLOCK_AUX_OFFSET + sizeof(Clo
 constexpr size_t OFF_SUMOUT = OFF_PART + align_up(SUM_BLOCKS * 3 * sizeof(double), ALIGN);
 constexpr size_t OFF_SRCTAB = OFF_SUMOUT + 256;
 
-size_t stage_off_of(const fvna_params* p)
+size_t rinv_off_of(const fvna_params* p)
 {
     return OFF_SRCTAB + align_up(4 * (size_t)p->ny * sizeof(double), ALIGN);
+}
+
+size_t stage_off_of(const fvna_params* p)
+{
+    return rinv_off_of(p) + align_up(((size_t)p->ny + 2 * RINV_PAD) * sizeof(double), ALIGN);
+}
+
+// The per-row 1/r table of an axisymmetric grid (nothing for a Cartesian one).
+static fvna_status fill_rinv(SimDesc& d, const fvna_params* p, char* scratch, hipStream_t stream)
+{
+    d.rinv = nullptr;
+    if (p->geometry != FVNA_AXISYMMETRIC) return FVNA_OK;
+    void* tab = scratch + rinv_off_of(p);
+    const int n = p->ny + 2 * RINV_PAD;
+    if (p->precision == FVNA_F64)
+        hipLaunchKernelGGL(k_rinv_table<double>, dim3((n + 255) / 256), dim3(256), 0, stream, (double*)tab, p->ny);
+    else
+        hipLaunchKernelGGL(k_rinv_table<float>, dim3((n + 255) / 256), dim3(256), 0, stream, (float*)tab, p->ny);
+    HIP_TRY(hipGetLastError());
+    d.rinv = tab;
+    return FVNA_OK;
 }
 
 size_t stage_cells_of(const fvna_params* p)
@@ -891,6 +923,12 @@ fvna_status fvna_create(const fvna_params* p, void* state_a, void* state_b, void
         (void)hipStreamDestroy(c->cap);
         delete c;
         return fail(FVNA_E_HIP, "cannot clear the state buffers");
+    }
+    s = fill_rinv(c->d, p, c->scratch, c->stream);
+    if (s) {
+        (void)hipStreamDestroy(c->cap);
+        delete c;
+        return s;
     }
     s = reset_clock(c, 0.0, p->dt0 > 0 ? p->dt0 * p->c0 / p->dx : 0.0, 0);
     if (s) {
@@ -1531,6 +1569,11 @@ fvna_status fvna_batch_create(int32_t n, const fvna_params* per_sim, void* const
         int tr = p.tile_rows ? p.tile_rows : (tuned.empty() ? BATCH_TILE_ROWS : tuned[k]);
         char* sc = (char*)bufs[3 * k + 2];
         fill_desc(d, &p, bufs[3 * k], bufs[3 * k + 1], (Clock*)(sc + OFF_CLOCK), tr, false);
+        const fvna_status sr = fill_rinv(d, &p, sc, b->stream);
+        if (sr) {
+            delete b;
+            return sr;
+        }
         b->d.push_back(d);
         b->scratch.push_back(sc);
     }
