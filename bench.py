@@ -44,18 +44,18 @@ BYTES_PER_CELL = {"f64": 48, "f32": 24, "f32_f16store": 12, "f32_bf16store": 12}
 # after any change they report null until profiled again.
 PMC_SOURCES = ("csrc/fvna_device.hpp", "csrc/fvna_step.hpp", "csrc/fvna_runtime.hip", "build.py")
 _PROFILED = {
-    "csrc/fvna_device.hpp": "854f213066db88703d843e94fc11a394f1ecd65ac8e597ea6dbbc2eeedef452f",
+    "csrc/fvna_device.hpp": "e8a79044eebcf6e19e0827735f2385e5190242fcd93d8f0951e51202d2ddb50c",
     "csrc/fvna_step.hpp": "a9e84437ccfeefe0500bc34f950718571f6c39e84c9e7b8d6134cc1fc4995563",
-    "csrc/fvna_runtime.hip": "3918adf77604081eac641ee11673ca1e7aff655fd1be5d44cebae7fa6e217a1c",
+    "csrc/fvna_runtime.hip": "0d2f8bb9b9116e5a8e1603e80e57027609bc6f354015411944941212688ed2a5",
     "build.py": "02eda4061ab4ab18fbd0c2e868524ec4e9acf39f5fa26d0513e48c2fca74259e",
 }
 PMC = {
     # profiles/k_step_f64_gaussian4096.md
-    "k_step<double,double,0>": {"nx": 4096, "ny": 4096, "fetch_bytes": 4.1996e+08, "write_bytes": 4.0523e+08,
+    "k_step<double,double,0>": {"nx": 4096, "ny": 4096, "fetch_bytes": 4.1953e+08, "write_bytes": 4.0525e+08,
                                 "valu_lane_ops_per_cell": 399.6, "valu_issue_cycles_per_cell": 26.49,
                                 "sources": _PROFILED},
     # profiles/k_step_f32_gaussian4096.md
-    "k_step<float,float,0>": {"nx": 4096, "ny": 4096, "fetch_bytes": 2.1502e+08, "write_bytes": 2.0448e+08,
+    "k_step<float,float,0>": {"nx": 4096, "ny": 4096, "fetch_bytes": 2.1497e+08, "write_bytes": 2.0450e+08,
                               "valu_lane_ops_per_cell": 300.8, "valu_issue_cycles_per_cell": 19.75,
                               "sources": _PROFILED},
 }
